@@ -1,0 +1,173 @@
+"""ctypes binding for ``oracle.c``.  TEST INFRASTRUCTURE ONLY.
+
+The C source is compiled with gcc, -O2 -ffp-contract=off and no fast-math,
+so every fp32 operation is one IEEE-rounded SSE instruction in source order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OR_OK = 0
+OR_ERR_INVALID_ARG = 1
+OR_ERR_RANGE = 3
+NONE = 0xFFFFFFFF
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin",
+          "-msse2", "-mfpmath=sse", "-fPIC", "-shared", "-Wall", "-Wextra"]
+
+
+class Stats(C.Structure):
+    _fields_ = [("bbox_tests", C.c_uint64), ("covered", C.c_uint64),
+                ("survivors", C.c_uint64), ("clipped", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so (always when ``force``)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            lib = C.CDLL(build())
+            f32p = C.POINTER(C.c_float)
+            u8p = C.POINTER(C.c_uint8)
+            u32p = C.POINTER(C.c_uint32)
+            i64p = C.POINTER(C.c_int64)
+            lib.or_focal.restype = C.c_float
+            lib.or_focal.argtypes = [C.c_uint32, C.c_double]
+            lib.or_pose_check.restype = C.c_int
+            lib.or_pose_check.argtypes = [f32p, f32p, f32p, C.c_uint32, C.c_uint32,
+                                          C.c_double, C.c_float]
+            lib.or_render_view.restype = C.c_int
+            lib.or_render_view.argtypes = [f32p, C.c_uint32, u8p, u32p, C.c_uint32,
+                                           C.c_uint32, C.c_uint32, C.c_double, C.c_float,
+                                           f32p, u8p, f32p, u32p, f32p, u32p,
+                                           C.POINTER(Stats)]
+            lib.or_coverage_count.restype = C.c_int
+            lib.or_coverage_count.argtypes = [f32p, C.c_uint32, u32p, C.c_uint32,
+                                              C.c_uint32, C.c_uint32, C.c_double, C.c_float,
+                                              f32p, u32p, C.POINTER(Stats)]
+            lib.or_project_point.restype = C.c_int
+            lib.or_project_point.argtypes = [f32p, f32p, C.c_uint32, C.c_uint32, C.c_double,
+                                             C.c_float, i64p, i64p, f32p]
+            _lib = lib
+    return _lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _geom(positions, colors, indices):
+    pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
+    idx = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
+    col = None if colors is None else np.ascontiguousarray(colors, np.uint8).reshape(-1, 3)
+    return pos, col, idx
+
+
+def focal(W: int, hfov_deg: float) -> float:
+    return float(_load().or_focal(W, hfov_deg))
+
+
+def pose_check(lo, hi, pose, W, H, hfov_deg=90.0, near_m=0.01) -> int:
+    lo = np.ascontiguousarray(lo, np.float32)
+    hi = np.ascontiguousarray(hi, np.float32)
+    pose = np.ascontiguousarray(pose, np.float32)
+    return int(_load().or_pose_check(_ptr(lo, C.c_float), _ptr(hi, C.c_float),
+                                     _ptr(pose, C.c_float), W, H, hfov_deg, near_m))
+
+
+def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.01,
+                raw=False):
+    """Render one view.  Returns dict(rgb [H,W,3] u8, depth [H,W] f32,
+    tri [H,W] u32, stats) and, with ``raw``, rho [H,W] f32 and key [H,W] u32.
+    Raises on a non-OK status."""
+    pos, col, idx = _geom(positions, colors, indices)
+    pose = np.ascontiguousarray(pose, np.float32).reshape(12)
+    rgb = np.empty((H, W, 3), np.uint8)
+    depth = np.empty((H, W), np.float32)
+    tri = np.empty((H, W), np.uint32)
+    rho = np.empty((H, W), np.float32) if raw else None
+    key = np.empty((H, W), np.uint32) if raw else None
+    st = Stats()
+    rc = _load().or_render_view(_ptr(pos, C.c_float), pos.shape[0], _ptr(col, C.c_uint8),
+                                _ptr(idx, C.c_uint32), idx.shape[0], W, H, hfov_deg, near_m,
+                                _ptr(pose, C.c_float), _ptr(rgb, C.c_uint8),
+                                _ptr(depth, C.c_float), _ptr(tri, C.c_uint32),
+                                _ptr(rho, C.c_float), _ptr(key, C.c_uint32), C.byref(st))
+    if rc != OR_OK:
+        raise OracleError(rc)
+    out = {"rgb": rgb, "depth": depth, "tri": tri, "stats": st.as_dict()}
+    if raw:
+        out["rho"] = rho
+        out["key"] = key
+    return out
+
+
+def coverage_count(positions, indices, W, H, pose, hfov_deg=90.0, near_m=0.01):
+    pos, _, idx = _geom(positions, None, indices)
+    pose = np.ascontiguousarray(pose, np.float32).reshape(12)
+    cnt = np.empty((H, W), np.uint32)
+    st = Stats()
+    rc = _load().or_coverage_count(_ptr(pos, C.c_float), pos.shape[0], _ptr(idx, C.c_uint32),
+                                   idx.shape[0], W, H, hfov_deg, near_m, _ptr(pose, C.c_float),
+                                   _ptr(cnt, C.c_uint32), C.byref(st))
+    if rc != OR_OK:
+        raise OracleError(rc)
+    return cnt, st.as_dict()
+
+
+def project_point(P, pose, W, H, hfov_deg=90.0, near_m=0.01):
+    """(X, Y, rw) in 1/256 px for a world point, or None behind the near plane."""
+    P = np.ascontiguousarray(P, np.float32).reshape(3)
+    pose = np.ascontiguousarray(pose, np.float32).reshape(12)
+    X, Y, rw = C.c_int64(), C.c_int64(), C.c_float()
+    rc = _load().or_project_point(_ptr(P, C.c_float), _ptr(pose, C.c_float), W, H, hfov_deg,
+                                  near_m, C.byref(X), C.byref(Y), C.byref(rw))
+    if rc == 1:
+        return None
+    if rc != OR_OK:
+        raise OracleError(rc)
+    return int(X.value), int(Y.value), float(rw.value)
+
+
+def render_views(positions, colors, indices, W, H, poses, hfov_deg=90.0, near_m=0.01,
+                 threads=1):
+    """Render several views, one view per thread (ctypes releases the GIL)."""
+    poses = np.asarray(poses, np.float32).reshape(-1, 12)
+    pos, col, idx = _geom(positions, colors, indices)
+    if threads <= 1:
+        return [render_view(pos, col, idx, W, H, p, hfov_deg, near_m) for p in poses]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda p: render_view(pos, col, idx, W, H, p, hfov_deg, near_m), poses))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc):
+        super().__init__(f"oracle status {rc}")
+        self.status = rc

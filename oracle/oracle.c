@@ -1,0 +1,432 @@
+/*
+ * oracle.c -- plain, slow CPU reference renderer.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this file's library.  The rendering library never links, calls or
+ * falls back to it, and the two share no code.
+ *
+ * What it computes (the paper's sensor model, Sec. 4 "Sensory input" and
+ * Sec. 3 "Rendering engine"): for a static triangle mesh with per-vertex
+ * colours and a pinhole camera of given resolution and horizontal field of
+ * view, the colour image and the "idealized" depth image seen from a camera
+ * pose, in one pass that also yields the visible triangle per pixel.  The
+ * paper gives no rasterisation rules; the written definition below fixes
+ * them (camera convention, planar depth, near plane, 8-bit sub-pixel snap,
+ * top-left fill rule, nearest-wins with a smaller-id tie break, perspective
+ * correct colour).  Every floating point step is fp32 with one rounding per
+ * operation, in the order written (compile with -ffp-contract=off, SSE math).
+ *
+ * Published methods restated here: Pineda edge functions (1988); the
+ * top-left fill rule with 8 sub-pixel bits; Sutherland-Hodgman clipping
+ * against one plane (1974); perspective-correct interpolation through 1/w
+ * (Heckbert & Moreton 1991); z-buffer visibility.
+ *
+ * Steps, per view, for each triangle in index order:
+ *   1. transform to camera space          (pose -> Xc, Yc, w = -Zc)
+ *   2. clip against w >= near              (0, 1 or 2 sub-triangles)
+ *   3. project and snap to 1/256 px        (X, Y int64, rw = 1/w)
+ *   4. orient (A > 0), drop A == 0, bbox   (pixel range in the viewport)
+ *   5. for each pixel centre in the bbox: coverage by three edge functions
+ *      with the top-left rule, key rho = interpolated 1/w, keep the largest
+ *      rho (smaller key on ties)
+ * and finally resolve each pixel: depth = 1/rho, colour interpolated with
+ * perspective-correct weights, triangle index.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_INVALID_ARG 1
+#define OR_ERR_RANGE 3
+
+#define OR_NONE 0xFFFFFFFFu
+#define OR_DOMAIN 536870912.0f /* 2^29: |X|, |Y| in 1/256 px must stay below */
+
+typedef struct {
+    uint64_t bbox_tests; /* pixel centres examined (sum of clipped bbox areas) */
+    uint64_t covered;    /* (sub-triangle, pixel) pairs that pass coverage    */
+    uint64_t survivors;  /* sub-triangles with a non-empty viewport bbox      */
+    uint64_t clipped;    /* triangles that straddle the near plane            */
+} or_stats;
+
+/* camera-space vertex with colour (0..255 as float) */
+typedef struct {
+    float x, y, w;
+    float c[3];
+} cvert;
+
+/* snapped screen vertex */
+typedef struct {
+    int64_t X, Y;
+    float rw;
+    float c[3];
+} svert;
+
+/* ------------------------------------------------------------------ a1 */
+/* Sensor constants.  The paper's sensor has a square 256^2 image with a
+ * 90-degree field of view (Sec. 4 "Sensory input"); the focal length in
+ * pixels is W / (2 tan(HFOV/2)), evaluated in double and rounded once. */
+float or_focal(uint32_t W, double hfov_deg)
+{
+    double f = (double)W / (2.0 * tan(hfov_deg * 3.14159265358979323846 / 360.0));
+    return (float)f;
+}
+
+/* Static fixed-point domain check for one pose: every vertex of the scene
+ * (inside the given axis-aligned box) that lies at w >= near must project
+ * to |X|, |Y| < 2^29 with a factor-two margin.  In double: the largest
+ * distance D from the camera to a box corner bounds |Xc| and |Yc|, and the
+ * projection is at most D * f * 256 / near + (W or H) * 128.  The rotation
+ * must be orthonormal to 1e-4 (max abs entry of R^T R - I). */
+int or_pose_check(const float *lo, const float *hi, const float *pose, uint32_t W,
+                  uint32_t H, double hfov_deg, float near_m)
+{
+    const float *R = pose + 3;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += (double)R[3 * k + a] * (double)R[3 * k + b];
+            if (fabs(s - (a == b ? 1.0 : 0.0)) > 1e-4) return OR_ERR_INVALID_ARG;
+        }
+    for (int k = 0; k < 12; ++k)
+        if (!isfinite(pose[k])) return OR_ERR_INVALID_ARG;
+    double D = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double v = (c >> a) & 1 ? hi[a] : lo[a];
+            double d = v - (double)pose[a];
+            d2 += d * d;
+        }
+        if (d2 > D) D = d2;
+    }
+    D = sqrt(D);
+    double fS = (double)or_focal(W, hfov_deg) * 256.0;
+    double m = (double)(W > H ? W : H) * 128.0;
+    if (D * fS / (double)near_m + m >= 268435456.0 /* 2^28 */) return OR_ERR_RANGE;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ a2 */
+/* world -> camera: d = P - p, camera coordinates are R^T d with R the
+ * row-major world-from-camera rotation; the camera looks along -Z so the
+ * depth coordinate is w = -Zc. */
+static void to_camera(const float *P, const float *pose, cvert *v)
+{
+    const float *R = pose + 3;
+    float dx = P[0] - pose[0];
+    float dy = P[1] - pose[1];
+    float dz = P[2] - pose[2];
+    float xc = (R[0] * dx + R[3] * dy) + R[6] * dz;
+    float yc = (R[1] * dx + R[4] * dy) + R[7] * dz;
+    float zc = (R[2] * dx + R[5] * dy) + R[8] * dz;
+    v->x = xc;
+    v->y = yc;
+    v->w = -zc;
+}
+
+/* ------------------------------------------------------------------ a3 */
+/* Sutherland-Hodgman against the single plane w >= near.  Walk the edges
+ * v0->v1, v1->v2, v2->v0; emit the start vertex when inside, then the
+ * crossing point when the edge crosses the plane.  The crossing is always
+ * interpolated from the inside end towards the outside end, so two
+ * triangles that share the edge produce the same point.  Returns the
+ * polygon size (0, 3 or 4). */
+static int clip_near(const cvert in[3], float zn, cvert out[4])
+{
+    int n = 0;
+    for (int k = 0; k < 3; ++k) {
+        const cvert *a = &in[k];
+        const cvert *b = &in[(k + 1) % 3];
+        int ia = a->w >= zn;
+        int ib = b->w >= zn;
+        if (ia) out[n++] = *a;
+        if (ia != ib) {
+            const cvert *s = ia ? a : b; /* inside end */
+            const cvert *o = ia ? b : a; /* outside end */
+            float t = (s->w - zn) / (s->w - o->w);
+            cvert q;
+            q.x = s->x + t * (o->x - s->x);
+            q.y = s->y + t * (o->y - s->y);
+            for (int c = 0; c < 3; ++c) q.c[c] = s->c[c] + t * (o->c[c] - s->c[c]);
+            q.w = zn;
+            out[n++] = q;
+        }
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------ a4 */
+/* Perspective projection and snap to 8 sub-pixel bits (1/256 px), rounding
+ * half to even.  Pixel (i, j) has its centre at (i + 1/2, j + 1/2) px, i.e.
+ * (256 i + 128, 256 j + 128) in fixed point; image row 0 is the top, so
+ * camera +Y maps to decreasing rows. */
+static int project(const cvert *v, float fS, float cxS, float cyS, svert *s)
+{
+    float rw = 1.0f / v->w;
+    float xs = rintf(cxS + (v->x * fS) * rw);
+    float ys = rintf(cyS - (v->y * fS) * rw);
+    if (!(fabsf(xs) < OR_DOMAIN && fabsf(ys) < OR_DOMAIN)) return OR_ERR_RANGE;
+    s->X = (int64_t)xs;
+    s->Y = (int64_t)ys;
+    s->rw = rw;
+    for (int c = 0; c < 3; ++c) s->c[c] = v->c[c];
+    return OR_OK;
+}
+
+static int64_t floor_div256(int64_t a)
+{
+    /* floor(a / 256) for any sign */
+    int64_t q = a / 256;
+    if ((a % 256) != 0 && (a < 0)) q -= 1;
+    return q;
+}
+
+/* Edge k runs from vertex k+1 to vertex k+2 (mod 3); its function at
+ * (px, py) is dx*(py - ay) - dy*(px - ax), positive inside once A > 0.
+ * An edge is owned ("top-left") when dy < 0, or dy == 0 and dx > 0. */
+static int64_t edge_fn(const svert *a, const svert *b, int64_t px, int64_t py)
+{
+    int64_t dx = b->X - a->X, dy = b->Y - a->Y;
+    return dx * (py - a->Y) - dy * (px - a->X);
+}
+
+static int edge_owned(const svert *a, const svert *b)
+{
+    int64_t dx = b->X - a->X, dy = b->Y - a->Y;
+    return dy < 0 || (dy == 0 && dx > 0);
+}
+
+/* Per-pixel state while the scene is drawn (the z-buffer). */
+typedef struct {
+    float rho;       /* interpolated 1/w of the current winner, 0 = empty   */
+    uint32_t key;    /* 2 * triangle index + sub-triangle, OR_NONE = empty  */
+    float wgt[3];    /* b_k * rw_k of the winner at this pixel              */
+    float num;       /* (wgt0 + wgt1) + wgt2                                */
+    float col[3][3]; /* the winner's vertex colours                         */
+} zpix;
+
+typedef struct {
+    const float *pos;
+    uint32_t V;
+    const uint8_t *col;
+    const uint32_t *idx;
+    uint32_t T;
+    uint32_t W, H;
+    float fS, cxS, cyS, zn;
+    const float *pose;
+} view_in;
+
+/* Rasterise one snapped sub-triangle into the z-buffer, or, with count !=
+ * NULL, only count covering triangles per pixel. */
+static void raster_tri(const view_in *in, svert v[3], uint32_t key, zpix *zb,
+                       uint32_t *count, or_stats *st)
+{
+    int64_t A = (v[1].X - v[0].X) * (v[2].Y - v[0].Y) - (v[1].Y - v[0].Y) * (v[2].X - v[0].X);
+    if (A == 0) return;
+    if (A < 0) {
+        svert t = v[1];
+        v[1] = v[2];
+        v[2] = t;
+        A = -A;
+    }
+    int64_t minX = v[0].X, maxX = v[0].X, minY = v[0].Y, maxY = v[0].Y;
+    for (int k = 1; k < 3; ++k) {
+        if (v[k].X < minX) minX = v[k].X;
+        if (v[k].X > maxX) maxX = v[k].X;
+        if (v[k].Y < minY) minY = v[k].Y;
+        if (v[k].Y > maxY) maxY = v[k].Y;
+    }
+    /* pixel centres 256 i + 128 inside [minX, maxX] */
+    int64_t i0 = floor_div256(minX - 128 + 255), i1 = floor_div256(maxX - 128);
+    int64_t j0 = floor_div256(minY - 128 + 255), j1 = floor_div256(maxY - 128);
+    if (i0 < 0) i0 = 0;
+    if (j0 < 0) j0 = 0;
+    if (i1 > (int64_t)in->W - 1) i1 = (int64_t)in->W - 1;
+    if (j1 > (int64_t)in->H - 1) j1 = (int64_t)in->H - 1;
+    if (i0 > i1 || j0 > j1) return;
+    st->survivors += 1;
+    st->bbox_tests += (uint64_t)((i1 - i0 + 1) * (j1 - j0 + 1));
+
+    int owned[3];
+    for (int k = 0; k < 3; ++k) owned[k] = edge_owned(&v[(k + 1) % 3], &v[(k + 2) % 3]);
+    float invA = 1.0f / (float)A;
+
+    for (int64_t j = j0; j <= j1; ++j) {
+        for (int64_t i = i0; i <= i1; ++i) {
+            int64_t px = 256 * i + 128, py = 256 * j + 128;
+            int64_t E[3];
+            int cov = 1;
+            for (int k = 0; k < 3; ++k) {
+                E[k] = edge_fn(&v[(k + 1) % 3], &v[(k + 2) % 3], px, py);
+                if (!(E[k] > 0 || (E[k] == 0 && owned[k]))) cov = 0;
+            }
+            if (!cov) continue;
+            st->covered += 1;
+            size_t p = (size_t)j * in->W + (size_t)i;
+            if (count) {
+                count[p] += 1;
+                continue;
+            }
+            float b0 = (float)E[0], b1 = (float)E[1], b2 = (float)E[2];
+            float w0 = b0 * v[0].rw, w1 = b1 * v[1].rw, w2 = b2 * v[2].rw;
+            float num = (w0 + w1) + w2;
+            float rho = num * invA;
+            zpix *z = &zb[p];
+            if (rho > z->rho || (rho == z->rho && key < z->key)) {
+                z->rho = rho;
+                z->key = key;
+                z->wgt[0] = w0;
+                z->wgt[1] = w1;
+                z->wgt[2] = w2;
+                z->num = num;
+                for (int k = 0; k < 3; ++k)
+                    for (int c = 0; c < 3; ++c) z->col[k][c] = v[k].c[c];
+            }
+        }
+    }
+}
+
+static int draw_view(const view_in *in, zpix *zb, uint32_t *count, or_stats *st)
+{
+    for (uint32_t t = 0; t < in->T; ++t) {
+        cvert cv[3];
+        for (int k = 0; k < 3; ++k) {
+            uint32_t vi = in->idx[3 * (size_t)t + k];
+            to_camera(in->pos + 3 * (size_t)vi, in->pose, &cv[k]);
+            for (int c = 0; c < 3; ++c)
+                cv[k].c[c] = in->col ? (float)in->col[3 * (size_t)vi + c] : 255.0f;
+        }
+        cvert poly[4];
+        int n = clip_near(cv, in->zn, poly);
+        if (n == 0) continue;
+        if (!(cv[0].w >= in->zn && cv[1].w >= in->zn && cv[2].w >= in->zn)) st->clipped += 1;
+        svert sp[4];
+        for (int k = 0; k < n; ++k)
+            if (project(&poly[k], in->fS, in->cxS, in->cyS, &sp[k]) != OR_OK) return OR_ERR_RANGE;
+        /* fan: (q0, q1, q2) and, for a quad, (q0, q2, q3) */
+        for (int s = 0; s + 2 < n; ++s) {
+            svert tri[3] = {sp[0], sp[s + 1], sp[s + 2]};
+            raster_tri(in, tri, 2u * t + (uint32_t)s, zb, count, st);
+        }
+    }
+    return OR_OK;
+}
+
+static int setup_view(view_in *in, const float *pos, uint32_t V, const uint8_t *col,
+                      const uint32_t *idx, uint32_t T, uint32_t W, uint32_t H,
+                      double hfov_deg, float near_m, const float *pose)
+{
+    if (W == 0 || H == 0 || W > 4096 || H > 4096) return OR_ERR_INVALID_ARG;
+    if (!(hfov_deg > 0.0 && hfov_deg < 180.0) || !(near_m > 0.0f)) return OR_ERR_INVALID_ARG;
+    if (T >= 0x7FFFFFFFu) return OR_ERR_INVALID_ARG;
+    for (size_t k = 0; k < 3 * (size_t)T; ++k)
+        if (idx[k] >= V) return OR_ERR_INVALID_ARG;
+    in->pos = pos;
+    in->V = V;
+    in->col = col;
+    in->idx = idx;
+    in->T = T;
+    in->W = W;
+    in->H = H;
+    in->fS = or_focal(W, hfov_deg) * 256.0f;
+    in->cxS = (float)W * 128.0f;
+    in->cyS = (float)H * 128.0f;
+    in->zn = near_m;
+    in->pose = pose;
+    return OR_OK;
+}
+
+/* Render one view.  Outputs (any may be NULL): rgb [H][W][3] uint8,
+ * depth [H][W] float (planar metres, 0 = no hit), tri [H][W] uint32 (index
+ * of the visible triangle, OR_NONE = no hit), rho [H][W] float and key
+ * [H][W] uint32 (the raw z-buffer).  Positions [V][3] float, colours
+ * [V][3] uint8 (NULL = white), indices [T][3] uint32. */
+int or_render_view(const float *pos, uint32_t V, const uint8_t *col, const uint32_t *idx,
+                   uint32_t T, uint32_t W, uint32_t H, double hfov_deg, float near_m,
+                   const float *pose, uint8_t *rgb, float *depth, uint32_t *tri,
+                   float *rho_out, uint32_t *key_out, or_stats *st)
+{
+    view_in in;
+    int rc = setup_view(&in, pos, V, col, idx, T, W, H, hfov_deg, near_m, pose);
+    if (rc != OR_OK) return rc;
+    or_stats local;
+    memset(&local, 0, sizeof local);
+    size_t np = (size_t)W * H;
+    zpix *zb = (zpix *)calloc(np, sizeof(zpix));
+    if (!zb) return OR_ERR_INVALID_ARG;
+    for (size_t p = 0; p < np; ++p) {
+        zb[p].rho = 0.0f;
+        zb[p].key = OR_NONE;
+    }
+    rc = draw_view(&in, zb, NULL, &local);
+    if (rc != OR_OK) {
+        free(zb);
+        return rc;
+    }
+    /* ------------------------------------------------------------ a7 */
+    for (size_t p = 0; p < np; ++p) {
+        const zpix *z = &zb[p];
+        int hit = z->key != OR_NONE;
+        if (rho_out) rho_out[p] = z->rho;
+        if (key_out) key_out[p] = z->key;
+        if (tri) tri[p] = hit ? (z->key >> 1) : OR_NONE;
+        if (depth) depth[p] = hit ? 1.0f / z->rho : 0.0f;
+        if (rgb) {
+            for (int c = 0; c < 3; ++c) {
+                uint8_t u = 0;
+                if (hit) {
+                    float val = ((z->wgt[0] * z->col[0][c] + z->wgt[1] * z->col[1][c]) +
+                                 z->wgt[2] * z->col[2][c]) / z->num;
+                    val = rintf(val);
+                    if (val < 0.0f) val = 0.0f;
+                    if (val > 255.0f) val = 255.0f;
+                    u = (uint8_t)val;
+                }
+                rgb[3 * p + c] = u;
+            }
+        }
+    }
+    free(zb);
+    if (st) *st = local;
+    return OR_OK;
+}
+
+/* Coverage-count mode: count[p] = number of sub-triangles whose coverage
+ * test accepts pixel p (no depth test).  Used for the watertightness
+ * invariant. */
+int or_coverage_count(const float *pos, uint32_t V, const uint32_t *idx, uint32_t T,
+                      uint32_t W, uint32_t H, double hfov_deg, float near_m,
+                      const float *pose, uint32_t *count, or_stats *st)
+{
+    view_in in;
+    int rc = setup_view(&in, pos, V, NULL, idx, T, W, H, hfov_deg, near_m, pose);
+    if (rc != OR_OK) return rc;
+    or_stats local;
+    memset(&local, 0, sizeof local);
+    memset(count, 0, sizeof(uint32_t) * (size_t)W * H);
+    rc = draw_view(&in, NULL, count, &local);
+    if (st) *st = local;
+    return rc;
+}
+
+/* Projection of a single point (closed-form checks): snapped fixed-point
+ * X, Y for a world point seen from a pose, or OR_ERR_RANGE / behind-camera
+ * (returns 1 when w < near). */
+int or_project_point(const float *P, const float *pose, uint32_t W, uint32_t H,
+                     double hfov_deg, float near_m, int64_t *X, int64_t *Y, float *rw)
+{
+    cvert v;
+    to_camera(P, pose, &v);
+    if (!(v.w >= near_m)) return 1;
+    svert s;
+    float fS = or_focal(W, hfov_deg) * 256.0f;
+    int rc = project(&v, fS, (float)W * 128.0f, (float)H * 128.0f, &s);
+    if (rc != OR_OK) return rc;
+    *X = s.X;
+    *Y = s.Y;
+    *rw = s.rw;
+    return OR_OK;
+}

@@ -1,0 +1,14 @@
+"""Seeded synthetic inputs shared by the oracle tests and the HIP path.
+
+Holds scene meshes, poses and walks only; none of the rendering arithmetic.
+"""
+from .scenes import (Rect, Scene, make_room, make_apartment, jitter_positions,
+                     aabb, triangle_count, cell_for_target)
+from .walks import (pose_from_yaw, poses_from_states, random_poses, random_walks,
+                    random_free_states, blocked, SENSOR_HEIGHT)
+from . import configs
+
+__all__ = ["Rect", "Scene", "make_room", "make_apartment", "jitter_positions",
+           "aabb", "triangle_count", "cell_for_target", "pose_from_yaw",
+           "poses_from_states", "random_poses", "random_walks", "random_free_states",
+           "blocked", "SENSOR_HEIGHT", "configs"]
