@@ -1,0 +1,257 @@
+/*
+ * hab.h -- C ABI of the MI355X (gfx950) RGB + depth sensor renderer.
+ *
+ * The library renders colour and depth observations of static triangle
+ * meshes from camera poses, the sensor model of the Habitat simulator
+ * (arXiv:1904.01201): Sec. 3 "Design overview" (the simulator returns the
+ * sensory data of an agent's sensors), Sec. 3 "Rendering engine" (one pass
+ * produces colour, depth and the per-pixel visible triangle), Sec. 4
+ * "Sensory input" (pinhole sensor with a resolution and a field of view,
+ * depth sharing the colour sensor's pose and intrinsics), Appendix A "Key
+ * abstractions" (given the agents' state the Simulator provides the
+ * observations of all active sensors) and Sec. 3 "Efficient GPU
+ * throughput" (frames handed to the learning framework as GPU tensors,
+ * without a copy through host memory).
+ *
+ * Rendering definition (identical for every entry point, batch size, tile
+ * size or bin capacity):
+ *   - world is right-handed, metres, +Y up; a pose is the camera position
+ *     p[3] and the row-major world-from-camera rotation R[9]; the camera
+ *     looks along its -Z axis with +Y up and +X right;
+ *   - f = W / (2 tan(hfov/2)) px (rounded once to fp32), principal point at
+ *     (W/2, H/2), pixel (i, j) centred at (i + 1/2, j + 1/2), row 0 on top;
+ *   - geometry with planar depth w < near is clipped away (no far plane);
+ *   - vertices snap to 1/256 px (round half to even); coverage uses edge
+ *     functions with the top-left fill rule; both faces are drawn;
+ *   - the visible triangle has the largest interpolated 1/w, ties going to
+ *     the smaller triangle index; depth is planar (distance along the view
+ *     axis) in metres; colour is the perspective-correct interpolation of
+ *     the vertex colours rounded to uint8;
+ *   - no hit: depth 0, colour (0, 0, 0), triangle index HAB_NO_HIT.
+ *
+ * Memory: every output pointer is caller-owned device memory, contiguous,
+ * row-major: rgb [N][H][W][3] uint8, depth [N][H][W] float, tri
+ * [N][H][W] uint32.  The library never keeps an output pointer after the
+ * call returns, except inside a stepper (which keeps the pointers it was
+ * created with until it is destroyed).  Host arrays passed in are read
+ * during the call only.
+ *
+ * Errors: every function returns a hab_status; nothing throws across the
+ * boundary.  Argument errors are detected before any work is enqueued.
+ * Rendering is asynchronous on the given HIP stream; a device-side fault
+ * report (a vertex outside the fixed-point range, which validation makes
+ * unreachable) is sticky and read with hab_get_error after synchronising.
+ *
+ * Threading: a context is externally synchronised (one thread at a time);
+ * scenes are immutable after upload and may be used by any stream.  Work
+ * enqueued through one context on different streams is ordered by the
+ * context (each call waits for the previous call's use of the context's
+ * scratch memory).
+ */
+#ifndef HAB_H
+#define HAB_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HAB_OK = 0,
+    HAB_ERR_INVALID_ARG = 1,   /* bad pointer, size, index, sensor or pose          */
+    HAB_ERR_OUT_OF_MEMORY = 2, /* device or pinned host allocation failed           */
+    HAB_ERR_RANGE = 3,         /* pose/scene outside the fixed-point domain          */
+    HAB_ERR_DEVICE = 4,        /* a HIP call failed                                  */
+    HAB_ERR_NOT_READY = 5,     /* poll: the request has not completed yet            */
+    HAB_ERR_CAPACITY = 6       /* server: queue full / request larger than budget    */
+} hab_status;
+
+#define HAB_NO_HIT 0xFFFFFFFFu
+#define HAB_MAX_DIM 4096u
+
+enum { HAB_OUT_RGB = 1, HAB_OUT_DEPTH = 2, HAB_OUT_TRI = 4 };
+
+typedef struct hab_context hab_context;
+typedef struct hab_scene hab_scene;
+typedef struct hab_stepper hab_stepper;
+typedef struct hab_server hab_server;
+
+/* Triangle mesh on the host.  positions [V][3] float (metres), colors
+ * [V][3] uint8 RGB (NULL: all white), indices [T][3] uint32 (each < V).
+ * V >= 1, T < 2^30. */
+typedef struct {
+    const float *positions;
+    uint32_t num_vertices;
+    const uint8_t *colors;
+    const uint32_t *indices;
+    uint32_t num_triangles;
+} hab_mesh_desc;
+
+/* Sensor request.  width, height in [1, 4096]; hfov_deg in (0, 180);
+ * near_m > 0 (0 selects the default 0.01 m); outputs = OR of HAB_OUT_*
+ * (0 selects RGB | DEPTH). */
+typedef struct {
+    uint32_t width, height;
+    float hfov_deg;
+    float near_m;
+    uint32_t outputs;
+} hab_sensor_desc;
+
+/* Validated sensor (plain data, filled by hab_sensor_spec). */
+typedef struct {
+    uint32_t width, height, outputs;
+    float hfov_deg;
+    float f;       /* focal length in px, fp32 */
+    float near_m;
+} hab_sensor;
+
+/* Camera pose: world_from_camera.  position in metres, rotation row-major,
+ * orthonormal to 1e-4 (max |R^T R - I|). */
+typedef struct {
+    float position[3];
+    float rotation[9];
+} hab_pose;
+
+/* Per-view work-counters, filled on request (hab_render_opts.stats):
+ * survivors = sub-triangles whose snapped bounding box meets the viewport,
+ * bbox_tests = pixel centres inside those boxes, covered = (sub-triangle,
+ * pixel) pairs that pass the coverage test. */
+typedef struct {
+    uint64_t survivors;
+    uint64_t bbox_tests;
+    uint64_t covered;
+} hab_view_stats;
+
+/* Launch options.  Zero-initialised = defaults.  tile_size in {0, 8, 16,
+ * 32} (0: autotuned/default); bin_factor: per-view bin capacity as a
+ * multiple of the triangle count (0: default); tile_cap: entries a tile
+ * list may hold before the tile takes the overflow path (0: unlimited).
+ * None of these changes any output bit. */
+typedef struct {
+    uint32_t tile_size;
+    float bin_factor;
+    uint32_t tile_cap;
+    hab_view_stats *stats; /* host array [N] or NULL; written after completion */
+} hab_render_opts;
+
+/* One view of a heterogeneous batch: any scene, any sensor, own outputs
+ * (device pointers sized for that sensor; NULL for unwanted outputs). */
+typedef struct {
+    const hab_scene *scene;
+    const hab_sensor *sensor;
+    hab_pose pose;
+    uint8_t *out_rgb;
+    float *out_depth;
+    uint32_t *out_tri;
+} hab_view;
+
+/* ---------------------------------------------------------- lifetime */
+/* Create a context on HIP device `device` (its ordinal). */
+hab_status hab_init(int device, hab_context **out);
+/* Synchronise and free everything the context owns (scenes included). */
+hab_status hab_shutdown(hab_context *ctx);
+const char *hab_status_string(hab_status s);
+/* Sticky device-side error of this context (HAB_OK if none); call after
+ * the stream has been synchronised.  Reading it clears it. */
+hab_status hab_get_error(hab_context *ctx);
+
+/* ---------------------------------------------------------- scenes */
+/* Copy a mesh into device memory (HBM-resident until released).  The host
+ * arrays may be freed when the call returns (the copy is synchronous with
+ * respect to the host).  Fails with HAB_ERR_INVALID_ARG on an index >= V,
+ * a non-finite position, V == 0 or T >= 2^30. */
+hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *mesh, hipStream_t stream,
+                            hab_scene **out);
+hab_status hab_scene_release(hab_context *ctx, hab_scene *scene);
+/* Device bytes held by a scene, its counts and its bounding box. */
+hab_status hab_scene_info(const hab_scene *scene, uint32_t *num_vertices,
+                          uint32_t *num_triangles, uint64_t *device_bytes, float bbox_lo[3],
+                          float bbox_hi[3]);
+
+/* ---------------------------------------------------------- sensors */
+/* Validate a sensor request and fill the plain-data sensor. */
+hab_status hab_sensor_spec(const hab_sensor_desc *desc, hab_sensor *out);
+
+/* ---------------------------------------------------------- rendering */
+/* Render num_poses views of one scene with one sensor.  poses: host array.
+ * out_rgb / out_depth: device [N][H][W][3] uint8 / [N][H][W] float, or
+ * NULL.  Poses outside the fixed-point domain of this scene and sensor
+ * fail with HAB_ERR_RANGE before anything is enqueued. */
+hab_status hab_render(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
+                      const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb,
+                      float *out_depth, hipStream_t stream);
+/* As hab_render, plus the visible-triangle output (device [N][H][W]
+ * uint32 or NULL) and options (NULL = defaults).  With opts->stats set
+ * the call synchronises the stream before returning. */
+hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
+                         const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb,
+                         float *out_depth, uint32_t *out_tri, const hab_render_opts *opts,
+                         hipStream_t stream);
+/* Render a heterogeneous batch (different scenes, resolutions and output
+ * sets) in one launch sequence.  Views of the same scene are grouped so
+ * that each triangle is fetched once per group. */
+hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t num_views,
+                            const hab_render_opts *opts, hipStream_t stream);
+
+/* ---------------------------------------------------------- stepper */
+/* A fixed batch composition captured once as a HIP graph.  Each step
+ * takes new poses (host array [num_views]), validates them, stages them
+ * in pinned memory and replays the graph on the stream.  The views'
+ * output pointers are those given at creation. */
+hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t num_views,
+                              const hab_render_opts *opts, hipStream_t stream,
+                              hab_stepper **out);
+hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t stream);
+hab_status hab_stepper_destroy(hab_stepper *st);
+
+/* ---------------------------------------------------------- serving */
+typedef struct {
+    uint32_t num_streams;      /* concurrent batches in flight (default 2)       */
+    uint32_t max_batch;        /* views per launched batch (default 256)         */
+    uint64_t memory_budget;    /* scratch bytes for admitted work (default 8 GiB) */
+    uint32_t max_queue;        /* queued requests before submit refuses (64k)    */
+    uint32_t max_wait_us;      /* how long the batcher waits to fill a batch (0) */
+} hab_server_cfg;
+
+typedef struct {
+    uint64_t submit_ns;   /* host clock (CLOCK_MONOTONIC) at submit   */
+    uint64_t launch_ns;   /* batch launched                           */
+    uint64_t done_ns;     /* completion observed                      */
+    uint32_t batch_size;  /* views in the batch this request rode in  */
+    uint32_t batch_id;
+} hab_request_stats;
+
+typedef struct {
+    uint64_t submitted, completed, batches, rejected;
+    uint64_t peak_inflight_bytes;
+    uint32_t peak_batch;
+} hab_server_stats;
+
+/* Start the request loop (one host thread) on a context the caller then
+ * no longer uses directly until hab_server_destroy. */
+hab_status hab_server_create(hab_context *ctx, const hab_server_cfg *cfg, hab_server **out);
+/* Non-blocking: queue one view (its pointers must stay valid until the
+ * request completes).  Returns a ticket. */
+hab_status hab_server_submit(hab_server *srv, const hab_view *view, uint64_t *ticket);
+/* HAB_ERR_NOT_READY until the ticket's outputs are complete in device
+ * memory; then HAB_OK and, if stats is non-NULL, its timestamps. */
+hab_status hab_server_poll(hab_server *srv, uint64_t ticket, hab_request_stats *stats);
+hab_status hab_server_wait(hab_server *srv, uint64_t ticket, hab_request_stats *stats);
+hab_status hab_server_stats_get(hab_server *srv, hab_server_stats *out);
+/* Drain outstanding work, stop the loop, free server resources. */
+hab_status hab_server_destroy(hab_server *srv);
+
+/* ---------------------------------------------------------- autotune */
+/* Time the candidate tile sizes and bin capacities on a sample batch and
+ * remember the fastest for this batch class (scene size, resolution,
+ * output mix); later calls with opts->tile_size == 0 use it.  Results are
+ * identical for every choice. */
+hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint32_t num_views,
+                        hipStream_t stream, uint32_t *chosen_tile_size, float *chosen_bin_factor);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HAB_H */

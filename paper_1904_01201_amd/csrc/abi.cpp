@@ -1,0 +1,326 @@
+// extern "C" entry points: argument checks, device selection, no exceptions
+// across the boundary.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace habmi;
+
+namespace {
+
+// Make ctx's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <class F>
+hab_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return HAB_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return HAB_ERR_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hab_status_string(hab_status s)
+{
+    switch (s) {
+    case HAB_OK: return "ok";
+    case HAB_ERR_INVALID_ARG: return "invalid argument";
+    case HAB_ERR_OUT_OF_MEMORY: return "out of memory";
+    case HAB_ERR_RANGE: return "outside the fixed-point domain";
+    case HAB_ERR_DEVICE: return "device error";
+    case HAB_ERR_NOT_READY: return "not ready";
+    case HAB_ERR_CAPACITY: return "capacity exceeded";
+    }
+    return "unknown status";
+}
+
+hab_status hab_init(int device, hab_context **out)
+{
+    if (!out) return HAB_ERR_INVALID_ARG;
+    *out = nullptr;
+    return guarded([&]() -> hab_status {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+            return HAB_ERR_INVALID_ARG;
+        DeviceGuard g(device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        hab_context *ctx = new hab_context();
+        ctx->device = device;
+        ctx->ws.device = device;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            ctx->cu_count = prop.multiProcessorCount;
+        if (hipMalloc(&ctx->err, 256) != hipSuccess) {
+            (void)hipGetLastError();
+            delete ctx;
+            return HAB_ERR_OUT_OF_MEMORY;
+        }
+        if (hipMemset(ctx->err, 0, 256) != hipSuccess) {
+            (void)hipFree(ctx->err);
+            delete ctx;
+            return HAB_ERR_DEVICE;
+        }
+        *out = ctx;
+        return HAB_OK;
+    });
+}
+
+hab_status hab_shutdown(hab_context *ctx)
+{
+    if (!ctx) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (Scene *s : ctx->scenes) {
+            (void)hipFree(s->pos);
+            (void)hipFree(s->col);
+            (void)hipFree(s->idx);
+            delete static_cast<hab_scene *>(s);
+        }
+        ctx->scenes.clear();
+        if (ctx->err) (void)hipFree(ctx->err);
+        delete ctx;
+        return HAB_OK;
+    });
+}
+
+hab_status hab_get_error(hab_context *ctx)
+{
+    if (!ctx) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        DeviceGuard g(ctx->device);
+        uint32_t e = 0;
+        HAB_HIP(hipMemcpy(&e, ctx->err, 4, hipMemcpyDeviceToHost));
+        if (e) HAB_HIP(hipMemset(ctx->err, 0, 4));
+        if (e & kErrRange) return HAB_ERR_RANGE;
+        return e ? HAB_ERR_DEVICE : HAB_OK;
+    });
+}
+
+hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_t stream,
+                            hab_scene **out)
+{
+    if (!ctx || !m || !out) return HAB_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!m->positions || m->num_vertices == 0) return HAB_ERR_INVALID_ARG;
+    if (m->num_triangles >= (1u << 30)) return HAB_ERR_INVALID_ARG;
+    if (m->num_triangles && !m->indices) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        const uint32_t V = m->num_vertices, T = m->num_triangles;
+        for (uint64_t k = 0; k < 3ull * T; ++k)
+            if (m->indices[k] >= V) return HAB_ERR_INVALID_ARG;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint64_t k = 0; k < V; ++k)
+            for (int a = 0; a < 3; ++a) {
+                const float x = m->positions[3 * k + a];
+                if (!std::isfinite(x)) return HAB_ERR_INVALID_ARG;
+                lo[a] = std::min(lo[a], x);
+                hi[a] = std::max(hi[a], x);
+            }
+        std::vector<uint32_t> col(V);
+        for (uint64_t k = 0; k < V; ++k) {
+            if (m->colors)
+                col[k] = (uint32_t)m->colors[3 * k] | ((uint32_t)m->colors[3 * k + 1] << 8) |
+                         ((uint32_t)m->colors[3 * k + 2] << 16);
+            else
+                col[k] = 0xFFFFFFu;
+        }
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        hab_scene *s = new hab_scene();
+        s->device = ctx->device;
+        s->V = V;
+        s->T = T;
+        for (int a = 0; a < 3; ++a) {
+            s->lo[a] = lo[a];
+            s->hi[a] = hi[a];
+        }
+        const size_t bp = 12ull * V, bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
+        bool ok = hipMalloc((void **)&s->pos, bp) == hipSuccess &&
+                  hipMalloc((void **)&s->col, bc) == hipSuccess &&
+                  hipMalloc((void **)&s->idx, bi) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            (void)hipFree(s->pos);
+            (void)hipFree(s->col);
+            (void)hipFree(s->idx);
+            delete s;
+            return HAB_ERR_OUT_OF_MEMORY;
+        }
+        s->bytes = bp + bc + bi;
+        hipError_t e = hipMemcpyAsync(s->pos, m->positions, bp, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->col, col.data(), bc, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && T)
+            e = hipMemcpyAsync(s->idx, m->indices, 12ull * T, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            (void)hipFree(s->pos);
+            (void)hipFree(s->col);
+            (void)hipFree(s->idx);
+            delete s;
+            return HAB_ERR_DEVICE;
+        }
+        ctx->scenes.push_back(s);
+        *out = s;
+        return HAB_OK;
+    });
+}
+
+hab_status hab_scene_release(hab_context *ctx, hab_scene *scene)
+{
+    if (!ctx || !scene) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        auto it = std::find(ctx->scenes.begin(), ctx->scenes.end(), static_cast<Scene *>(scene));
+        if (it == ctx->scenes.end()) return HAB_ERR_INVALID_ARG;
+        DeviceGuard g(ctx->device);
+        // work that still reads the scene must finish first
+        HAB_HIP(hipDeviceSynchronize());
+        (void)hipFree(scene->pos);
+        (void)hipFree(scene->col);
+        (void)hipFree(scene->idx);
+        ctx->scenes.erase(it);
+        delete scene;
+        return HAB_OK;
+    });
+}
+
+hab_status hab_scene_info(const hab_scene *s, uint32_t *nv, uint32_t *nt, uint64_t *bytes,
+                          float lo[3], float hi[3])
+{
+    if (!s) return HAB_ERR_INVALID_ARG;
+    if (nv) *nv = s->V;
+    if (nt) *nt = s->T;
+    if (bytes) *bytes = s->bytes;
+    for (int a = 0; a < 3; ++a) {
+        if (lo) lo[a] = s->lo[a];
+        if (hi) hi[a] = s->hi[a];
+    }
+    return HAB_OK;
+}
+
+hab_status hab_sensor_spec(const hab_sensor_desc *d, hab_sensor *out)
+{
+    if (!d || !out) return HAB_ERR_INVALID_ARG;
+    if (d->width == 0 || d->height == 0 || d->width > HAB_MAX_DIM || d->height > HAB_MAX_DIM)
+        return HAB_ERR_INVALID_ARG;
+    if (!(d->hfov_deg > 0.0f && d->hfov_deg < 180.0f)) return HAB_ERR_INVALID_ARG;
+    const float near_m = d->near_m == 0.0f ? 0.01f : d->near_m;
+    if (!(near_m > 0.0f) || !std::isfinite(near_m)) return HAB_ERR_INVALID_ARG;
+    const uint32_t outputs = d->outputs ? d->outputs : (HAB_OUT_RGB | HAB_OUT_DEPTH);
+    if (outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI)) return HAB_ERR_INVALID_ARG;
+    hab_sensor s;
+    s.width = d->width;
+    s.height = d->height;
+    s.outputs = outputs;
+    s.hfov_deg = d->hfov_deg;
+    s.f = (float)((double)d->width / (2.0 * std::tan((double)d->hfov_deg * 3.14159265358979323846 / 360.0)));
+    s.near_m = near_m;
+    if (!(s.f > 0.0f) || !std::isfinite(s.f)) return HAB_ERR_INVALID_ARG;
+    *out = s;
+    return HAB_OK;
+}
+
+static hab_status render_common(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
+                                const hab_pose *poses, uint32_t n, uint8_t *rgb, float *depth,
+                                uint32_t *tri, const hab_render_opts *opts, hipStream_t stream)
+{
+    if (!ctx || !scene || !sensor || (!poses && n)) return HAB_ERR_INVALID_ARG;
+    if (n == 0) return HAB_OK;
+    hab_status st = validate_sensor(sensor);
+    if (st != HAB_OK) return st;
+    if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
+        return HAB_ERR_INVALID_ARG;
+    if (opts && opts->bin_factor < 0.0f) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        std::vector<ViewReq> req(n);
+        const size_t px = (size_t)sensor->width * sensor->height;
+        for (uint32_t k = 0; k < n; ++k) {
+            hab_status s2 = validate_pose(scene, sensor, &poses[k]);
+            if (s2 != HAB_OK) return s2;
+            ViewReq &r = req[k];
+            r.scene = scene;
+            r.sensor = *sensor;
+            r.pose = poses[k];
+            r.rgb = (rgb && (sensor->outputs & HAB_OUT_RGB)) ? rgb + 3 * px * k : nullptr;
+            r.depth = (depth && (sensor->outputs & HAB_OUT_DEPTH)) ? depth + px * k : nullptr;
+            r.tri = tri ? tri + px * k : nullptr;
+        }
+        PlanOpts o;
+        if (opts) {
+            o.tile_size = opts->tile_size;
+            o.bin_factor = opts->bin_factor;
+            o.tile_cap = opts->tile_cap;
+        }
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        return render_all(ctx, ctx->ws, req.data(), n, o, stream, opts ? opts->stats : nullptr);
+    });
+}
+
+hab_status hab_render(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
+                      const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb, float *out_depth,
+                      hipStream_t stream)
+{
+    return render_common(ctx, scene, sensor, poses, num_poses, out_rgb, out_depth, nullptr, nullptr,
+                         stream);
+}
+
+hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
+                         const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb,
+                         float *out_depth, uint32_t *out_tri, const hab_render_opts *opts,
+                         hipStream_t stream)
+{
+    return render_common(ctx, scene, sensor, poses, num_poses, out_rgb, out_depth, out_tri, opts,
+                         stream);
+}
+
+hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t n,
+                            const hab_render_opts *opts, hipStream_t stream)
+{
+    if (!ctx || (!views && n)) return HAB_ERR_INVALID_ARG;
+    if (n == 0) return HAB_OK;
+    if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
+        return HAB_ERR_INVALID_ARG;
+    if (opts && opts->bin_factor < 0.0f) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        std::vector<ViewReq> req(n);
+        for (uint32_t k = 0; k < n; ++k) {
+            hab_status s2 = to_view_req(views[k], req[k]);
+            if (s2 != HAB_OK) return s2;
+        }
+        PlanOpts o;
+        if (opts) {
+            o.tile_size = opts->tile_size;
+            o.bin_factor = opts->bin_factor;
+            o.tile_cap = opts->tile_cap;
+        }
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        return render_all(ctx, ctx->ws, req.data(), n, o, stream, opts ? opts->stats : nullptr);
+    });
+}
+
+}  // extern "C"

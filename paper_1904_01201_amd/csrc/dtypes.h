@@ -1,0 +1,60 @@
+// Plain structures shared by the host runtime and the kernels.
+#pragma once
+#include <stdint.h>
+
+namespace habmi {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kOverflow = 0xFFFFFFFFu;   // tile offset marker: list not stored
+constexpr int kSetupBlock = 256;              // threads per block in setup
+constexpr int kBinBlock = 256;                // threads per block in count/scatter
+constexpr int kBinItems = 4;                  // survivors per thread in count/scatter
+constexpr int kScanBlock = 1024;
+
+// Error bits of the sticky device error word.
+constexpr uint32_t kErrRange = 1u;            // a vertex snapped outside |X|,|Y| < 2^29
+constexpr uint32_t kErrResolve = 2u;          // a winning key could not be rebuilt
+
+// One view of a launch.  16-byte aligned; 192 bytes.
+struct alignas(16) DView {
+    float p[3];
+    float R[9];                 // row-major world-from-camera
+    float fS, cxS, cyS, zn;     // f*256, W*128, H*128, near
+    uint32_t W, H;
+    uint32_t T;                 // triangles of the scene
+    uint32_t ts_log2;           // tile size 8/16/32 -> 3/4/5
+    const float *pos;           // [V][3]
+    const uint32_t *col;        // [V] packed R | G<<8 | B<<16
+    const uint32_t *idx;        // [T][3]
+    uint8_t *rgb;               // [H][W][3] or null
+    float *depth;               // [H][W] or null
+    uint32_t *tri;              // [H][W] or null
+    uint32_t tiles_x, tiles_y;
+    uint32_t tile_base;         // first entry in the per-tile arrays
+    uint32_t surv_base;         // first entry in the survivor arrays
+    uint32_t surv_cap;          // 2 T
+    uint32_t bin_base;          // first entry in the bin array
+    uint32_t bin_cap;           // entries available to this view
+    uint32_t tile_cap;          // entries one tile may hold (else overflow)
+    uint32_t pad[6];
+};
+static_assert(sizeof(DView) == 192, "DView layout");
+
+// A run of consecutive views that share one scene: setup fetches each
+// triangle once and transforms it for every view of the group.
+struct DGroup {
+    uint32_t first_view;
+    uint32_t num_views;
+    uint32_t T;
+    uint32_t block_start;       // first setup block of this group
+};
+
+// Per-view counters (zeroed at the start of every launch sequence).
+struct DViewCounters {
+    uint32_t surv_count;        // survivors appended by setup
+    uint32_t bin_used;          // entries the scan assigned
+    unsigned long long bbox_tests;
+    unsigned long long covered;
+};
+
+}  // namespace habmi

@@ -1,0 +1,420 @@
+// Host runtime: validation, workspace arena, launch planning and staging.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace habmi {
+
+static constexpr uint32_t kGroupMax = 16;           // views per setup group
+static constexpr float kDefaultBinFactor = 2.0f;
+static constexpr uint32_t kDefaultTile = 16;
+static constexpr uint64_t kIndexLimit = 1ull << 31; // per launch: survivors, bins, tiles
+
+static inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------- workspace
+Workspace::~Workspace()
+{
+    if (has_done) (void)hipEventSynchronize(done);
+    for (auto &s : slots) {
+        if (s.pending) (void)hipEventSynchronize(s.ev);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+    }
+    if (arena) (void)hipFree(arena);
+    if (done) (void)hipEventDestroy(done);
+}
+
+hab_status Workspace::ensure(size_t bytes)
+{
+    if (!done) HAB_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    if (bytes <= cap) return HAB_OK;
+    if (has_done) HAB_HIP(hipEventSynchronize(done));
+    if (arena) {
+        HAB_HIP(hipFree(arena));
+        arena = nullptr;
+        cap = 0;
+    }
+    size_t want = std::max(bytes, cap + cap / 2);
+    if (hipMalloc(&arena, want) != hipSuccess) {
+        arena = nullptr;
+        (void)hipGetLastError();
+        if (hipMalloc(&arena, bytes) != hipSuccess) {
+            arena = nullptr;
+            (void)hipGetLastError();
+            return HAB_ERR_OUT_OF_MEMORY;
+        }
+        want = bytes;
+    }
+    cap = want;
+    return HAB_OK;
+}
+
+hab_status Workspace::staging(size_t bytes, void **host, int *slot)
+{
+    Slot &s = slots[next];
+    *slot = next;
+    next = (next + 1) % kSlots;
+    if (!s.ev) HAB_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+    if (s.pending) {
+        HAB_HIP(hipEventSynchronize(s.ev));
+        s.pending = false;
+    }
+    if (s.cap < bytes) {
+        if (s.host) HAB_HIP(hipHostFree(s.host));
+        s.host = nullptr;
+        s.cap = 0;
+        size_t want = std::max(bytes, (size_t)64 << 10);
+        if (hipHostMalloc(&s.host, want, hipHostMallocDefault) != hipSuccess) {
+            s.host = nullptr;
+            (void)hipGetLastError();
+            return HAB_ERR_OUT_OF_MEMORY;
+        }
+        s.cap = want;
+    }
+    *host = s.host;
+    return HAB_OK;
+}
+
+// ---------------------------------------------------------------- validation
+static double focal_of(uint32_t W, double hfov_deg)
+{
+    return (double)W / (2.0 * std::tan(hfov_deg * 3.14159265358979323846 / 360.0));
+}
+
+hab_status validate_sensor(const hab_sensor *s)
+{
+    if (!s) return HAB_ERR_INVALID_ARG;
+    if (s->width == 0 || s->height == 0 || s->width > HAB_MAX_DIM || s->height > HAB_MAX_DIM)
+        return HAB_ERR_INVALID_ARG;
+    if (!(s->hfov_deg > 0.0f && s->hfov_deg < 180.0f)) return HAB_ERR_INVALID_ARG;
+    if (!(s->near_m > 0.0f) || !std::isfinite(s->near_m)) return HAB_ERR_INVALID_ARG;
+    if (s->outputs == 0 || (s->outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI)))
+        return HAB_ERR_INVALID_ARG;
+    if (s->f != (float)focal_of(s->width, s->hfov_deg)) return HAB_ERR_INVALID_ARG;
+    return HAB_OK;
+}
+
+// Static fixed-point domain check: with D the largest distance from the
+// camera to a corner of the scene's bounding box, every vertex at w >= near
+// projects to at most D f 256 / near + max(W, H) 128 in 1/256 px; requiring
+// that below 2^28 keeps |X|, |Y| < 2^29 with a factor-two margin for fp32
+// rounding.  The rotation must be orthonormal to 1e-4.
+hab_status validate_pose(const Scene *sc, const hab_sensor *s, const hab_pose *p)
+{
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->position[k])) return HAB_ERR_INVALID_ARG;
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(p->rotation[k])) return HAB_ERR_INVALID_ARG;
+    const float *R = p->rotation;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double d = 0.0;
+            for (int k = 0; k < 3; ++k) d += (double)R[3 * k + a] * (double)R[3 * k + b];
+            if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-4) return HAB_ERR_INVALID_ARG;
+        }
+    double D2 = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double x = ((c >> a) & 1) ? sc->hi[a] : sc->lo[a];
+            double d = x - (double)p->position[a];
+            d2 += d * d;
+        }
+        D2 = std::max(D2, d2);
+    }
+    double reach = std::sqrt(D2) * (double)s->f * 256.0 / (double)s->near_m +
+                   (double)std::max(s->width, s->height) * 128.0;
+    if (!(reach < 268435456.0)) return HAB_ERR_RANGE;
+    return HAB_OK;
+}
+
+hab_status to_view_req(const hab_view &hv, ViewReq &out)
+{
+    if (!hv.scene || !hv.sensor) return HAB_ERR_INVALID_ARG;
+    hab_status st = validate_sensor(hv.sensor);
+    if (st != HAB_OK) return st;
+    const Scene *sc = hv.scene;
+    st = validate_pose(sc, hv.sensor, &hv.pose);
+    if (st != HAB_OK) return st;
+    out.scene = sc;
+    out.sensor = *hv.sensor;
+    out.pose = hv.pose;
+    out.rgb = (hv.sensor->outputs & HAB_OUT_RGB) ? hv.out_rgb : nullptr;
+    out.depth = (hv.sensor->outputs & HAB_OUT_DEPTH) ? hv.out_depth : nullptr;
+    out.tri = hv.out_tri;
+    return HAB_OK;
+}
+
+// ---------------------------------------------------------------- autotune table
+uint32_t class_key(const Scene *sc, const hab_sensor *s)
+{
+    uint32_t tlog = 0;
+    while ((1u << tlog) < std::max<uint32_t>(sc->T, 1)) ++tlog;
+    uint32_t wlog = 0;
+    while ((1u << wlog) < std::max(s->width, s->height)) ++wlog;
+    return (tlog << 8) | (wlog << 3) | (s->outputs & 7u);
+}
+
+uint32_t choose_tile(hab_context *ctx, const Scene *sc, const hab_sensor *s, const PlanOpts &o,
+                     float *bin_factor)
+{
+    *bin_factor = o.bin_factor > 0.0f ? o.bin_factor : kDefaultBinFactor;
+    if (o.tile_size) return o.tile_size;
+    if (ctx) {
+        const uint32_t key = class_key(sc, s);
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        for (const Tuned &t : ctx->tuned)
+            if (t.key == key) {
+                if (o.bin_factor <= 0.0f) *bin_factor = t.bin_factor;
+                return t.ts;
+            }
+    }
+    return kDefaultTile;
+}
+
+// ---------------------------------------------------------------- planning
+static inline uint32_t ts_log2(uint32_t ts) { return ts == 8 ? 3u : ts == 16 ? 4u : 5u; }
+
+hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
+                      const PlanOpts &o, Plan &plan, std::vector<uint8_t> &desc)
+{
+    (void)ws;
+    if (n == 0 || n > kMaxViews) return HAB_ERR_INVALID_ARG;
+    plan.n = n;
+    plan.order.resize(n);
+    std::iota(plan.order.begin(), plan.order.end(), 0u);
+    std::stable_sort(plan.order.begin(), plan.order.end(),
+                     [&](uint32_t a, uint32_t b) { return v[a].scene < v[b].scene; });
+
+    std::vector<DView> dv(n);
+    std::vector<DGroup> groups;
+    std::vector<uint32_t> lview[3], lpre[3];
+    uint64_t tile_total = 0, surv_total = 0, bin_total = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        const ViewReq &r = v[plan.order[k]];
+        float bf;
+        uint32_t ts = choose_tile(ctx, r.scene, &r.sensor, o, &bf);
+        if (ts != 8 && ts != 16 && ts != 32) return HAB_ERR_INVALID_ARG;
+        DView &d = dv[k];
+        std::memset(&d, 0, sizeof d);
+        for (int a = 0; a < 3; ++a) d.p[a] = r.pose.position[a];
+        for (int a = 0; a < 9; ++a) d.R[a] = r.pose.rotation[a];
+        d.fS = r.sensor.f * 256.0f;
+        d.cxS = (float)r.sensor.width * 128.0f;
+        d.cyS = (float)r.sensor.height * 128.0f;
+        d.zn = r.sensor.near_m;
+        d.W = r.sensor.width;
+        d.H = r.sensor.height;
+        d.T = r.scene->T;
+        d.ts_log2 = ts_log2(ts);
+        d.pos = r.scene->pos;
+        d.col = r.scene->col;
+        d.idx = r.scene->idx;
+        d.rgb = r.rgb;
+        d.depth = r.depth;
+        d.tri = r.tri;
+        d.tiles_x = cdiv(d.W, ts);
+        d.tiles_y = cdiv(d.H, ts);
+        d.tile_base = (uint32_t)tile_total;
+        tile_total += (uint64_t)d.tiles_x * d.tiles_y;
+        d.surv_base = (uint32_t)surv_total;
+        d.surv_cap = 2u * d.T;
+        surv_total += d.surv_cap;
+        uint64_t bc = (uint64_t)std::ceil((double)bf * (double)d.T);
+        bc = std::max<uint64_t>(bc, 1024);
+        bc = std::min<uint64_t>(bc, kIndexLimit / 4);
+        d.bin_base = (uint32_t)bin_total;
+        d.bin_cap = (uint32_t)bc;
+        bin_total += bc;
+        d.tile_cap = o.tile_cap ? o.tile_cap : 0xFFFFFFFFu;
+        const int c = ts == 8 ? 0 : ts == 16 ? 1 : 2;
+        uint32_t pre = lview[c].empty() ? 0u : lpre[c].back() + dv[lview[c].back()].tiles_x * dv[lview[c].back()].tiles_y;
+        lview[c].push_back(k);
+        lpre[c].push_back(pre);
+    }
+    if (tile_total >= kIndexLimit || surv_total >= kIndexLimit || bin_total >= kIndexLimit)
+        return HAB_ERR_CAPACITY;
+
+    uint32_t setup_blocks = 0;
+    for (uint32_t k = 0; k < n;) {
+        uint32_t e = k + 1;
+        while (e < n && e - k < kGroupMax && v[plan.order[e]].scene == v[plan.order[k]].scene) ++e;
+        DGroup g;
+        g.first_view = k;
+        g.num_views = e - k;
+        g.T = dv[k].T;
+        g.block_start = setup_blocks;
+        setup_blocks += cdiv(g.T, kSetupBlock);
+        groups.push_back(g);
+        k = e;
+    }
+
+    // descriptor block
+    size_t off = 0;
+    plan.off_views = off;
+    off = align256(off + sizeof(DView) * n);
+    plan.off_groups = off;
+    off = align256(off + sizeof(DGroup) * groups.size());
+    for (int c = 0; c < 3; ++c) {
+        plan.off_lview[c] = off;
+        off = align256(off + 4 * lview[c].size());
+        plan.off_lpre[c] = off;
+        off = align256(off + 4 * lpre[c].size());
+    }
+    plan.desc_bytes = off;
+    desc.resize(off);
+    std::memcpy(desc.data() + plan.off_views, dv.data(), sizeof(DView) * n);
+    std::memcpy(desc.data() + plan.off_groups, groups.data(), sizeof(DGroup) * groups.size());
+    for (int c = 0; c < 3; ++c) {
+        if (!lview[c].empty()) {
+            std::memcpy(desc.data() + plan.off_lview[c], lview[c].data(), 4 * lview[c].size());
+            std::memcpy(desc.data() + plan.off_lpre[c], lpre[c].data(), 4 * lpre[c].size());
+        }
+    }
+    // scratch
+    plan.off_ctr = off;
+    off = align256(off + sizeof(DViewCounters) * n);
+    plan.off_tcount = off;
+    off = align256(off + 4 * tile_total);
+    plan.off_toff = off;
+    off = align256(off + 4 * tile_total);
+    plan.off_tcur = off;
+    off = align256(off + 4 * tile_total);
+    plan.off_skey = off;
+    off = align256(off + 4 * surv_total);
+    plan.off_sbox = off;
+    off = align256(off + 8 * surv_total);
+    plan.off_bins = off;
+    off = align256(off + 4 * bin_total);
+    plan.arena_bytes = off;
+
+    LaunchPlan &L = plan.L;
+    L = LaunchPlan{};
+    L.nviews = n;
+    L.ngroups = (uint32_t)groups.size();
+    L.setup_blocks = setup_blocks;
+    L.ntiles = (uint32_t)tile_total;
+    uint64_t ub = 0;
+    for (uint32_t k = 0; k < n; ++k) ub += cdiv(dv[k].surv_cap, kBinBlock * kBinItems);
+    L.bin_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ub, 8ull * (ctx ? ctx->cu_count : 256)));
+    L.nraster = 0;
+    for (int c = 0; c < 3; ++c) {
+        if (lview[c].empty()) continue;
+        RasterLaunch &R = L.raster[L.nraster++];
+        R.ts = c == 0 ? 8 : c == 1 ? 16 : 32;
+        R.nl = (uint32_t)lview[c].size();
+        const DView &last = dv[lview[c].back()];
+        R.blocks = lpre[c].back() + last.tiles_x * last.tiles_y;
+        R.lview = reinterpret_cast<const uint32_t *>(plan.off_lview[c]);   // bound later
+        R.lpre = reinterpret_cast<const uint32_t *>(plan.off_lpre[c]);
+    }
+    return HAB_OK;
+}
+
+void bind_plan(Plan &plan, void *arena, uint32_t *err)
+{
+    char *b = static_cast<char *>(arena);
+    LaunchPlan &L = plan.L;
+    L.views = reinterpret_cast<const DView *>(b + plan.off_views);
+    L.groups = reinterpret_cast<const DGroup *>(b + plan.off_groups);
+    L.ctr = reinterpret_cast<DViewCounters *>(b + plan.off_ctr);
+    L.tile_count = reinterpret_cast<uint32_t *>(b + plan.off_tcount);
+    L.tile_off = reinterpret_cast<uint32_t *>(b + plan.off_toff);
+    L.tile_cursor = reinterpret_cast<uint32_t *>(b + plan.off_tcur);
+    L.skey = reinterpret_cast<uint32_t *>(b + plan.off_skey);
+    L.sbox = reinterpret_cast<uint2 *>(b + plan.off_sbox);
+    L.bins = reinterpret_cast<uint32_t *>(b + plan.off_bins);
+    L.err = err;
+    for (int k = 0; k < L.nraster; ++k) {
+        RasterLaunch &R = L.raster[k];
+        const int c = R.ts == 8 ? 0 : R.ts == 16 ? 1 : 2;
+        R.lview = reinterpret_cast<const uint32_t *>(b + plan.off_lview[c]);
+        R.lpre = reinterpret_cast<const uint32_t *>(b + plan.off_lpre[c]);
+    }
+}
+
+Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context *ctx)
+{
+    Footprint f;
+    uint64_t bytes = 0, tiles = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        float bf;
+        uint32_t ts = choose_tile(ctx, v[k].scene, &v[k].sensor, o, &bf);
+        uint64_t nt = (uint64_t)cdiv(v[k].sensor.width, ts) * cdiv(v[k].sensor.height, ts);
+        tiles += nt;
+        uint64_t bc = std::max<uint64_t>((uint64_t)std::ceil((double)bf * v[k].scene->T), 1024);
+        bytes += 2ull * v[k].scene->T * 12ull + bc * 4ull + nt * 12ull + sizeof(DView) + 64;
+    }
+    f.desc_bytes = n * (sizeof(DView) + 32) + 4096;
+    f.arena_bytes = bytes + f.desc_bytes + 16 * 256;
+    (void)tiles;
+    return f;
+}
+
+// ---------------------------------------------------------------- launching
+hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
+                        const PlanOpts &o, hipStream_t s, hab_view_stats *stats)
+{
+    Plan plan;
+    hab_status st = build_plan(ctx, ws, v, n, o, plan, ws.desc);
+    if (st != HAB_OK) return st;
+    st = ws.ensure(plan.arena_bytes);
+    if (st != HAB_OK) return st;
+    if (ws.has_done && ws.last_stream != s) HAB_HIP(hipStreamWaitEvent(s, ws.done, 0));
+    void *host;
+    int slot;
+    st = ws.staging(plan.desc_bytes, &host, &slot);
+    if (st != HAB_OK) return st;
+    std::memcpy(host, ws.desc.data(), plan.desc_bytes);
+    HAB_HIP(hipMemcpyAsync(ws.arena, host, plan.desc_bytes, hipMemcpyHostToDevice, s));
+    HAB_HIP(hipEventRecord(ws.slots[slot].ev, s));
+    ws.slots[slot].pending = true;
+    bind_plan(plan, ws.arena, ctx->err);
+    HAB_HIP(launch_render(plan.L, s));
+    HAB_HIP(hipEventRecord(ws.done, s));
+    ws.has_done = true;
+    ws.last_stream = s;
+    if (stats) {
+        std::vector<DViewCounters> c(n);
+        HAB_HIP(hipMemcpyAsync(c.data(), plan.L.ctr, sizeof(DViewCounters) * n, hipMemcpyDeviceToHost, s));
+        HAB_HIP(hipStreamSynchronize(s));
+        for (uint32_t k = 0; k < n; ++k) {
+            hab_view_stats &o2 = stats[plan.order[k]];
+            o2.survivors = c[k].surv_count;
+            o2.bbox_tests = c[k].bbox_tests;
+            o2.covered = c[k].covered;
+        }
+    }
+    return HAB_OK;
+}
+
+hab_status render_all(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
+                      const PlanOpts &o, hipStream_t s, hab_view_stats *stats)
+{
+    uint32_t k = 0;
+    while (k < n) {
+        uint32_t e = k;
+        uint64_t surv = 0, bins = 0;
+        while (e < n && e - k < kMaxViews) {
+            float bf;
+            (void)choose_tile(ctx, v[e].scene, &v[e].sensor, o, &bf);
+            const uint64_t s2 = 2ull * v[e].scene->T;
+            const uint64_t b2 = std::max<uint64_t>((uint64_t)std::ceil((double)bf * v[e].scene->T), 1024);
+            if (e > k && (surv + s2 >= kIndexLimit / 2 || bins + b2 >= kIndexLimit / 2)) break;
+            surv += s2;
+            bins += b2;
+            ++e;
+        }
+        hab_status st = render_views(ctx, ws, v + k, e - k, o, s, stats ? stats + k : nullptr);
+        if (st != HAB_OK) return st;
+        k = e;
+    }
+    return HAB_OK;
+}
+
+}  // namespace habmi

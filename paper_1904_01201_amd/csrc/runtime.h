@@ -1,0 +1,141 @@
+// Host runtime of the renderer: context, resident scenes, workspace arena,
+// launch planner.  Internal; the public surface is include/hab.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/hab.h"
+#include "dtypes.h"
+#include "kernels.h"
+
+namespace habmi {
+
+#define HAB_HIP(x)                                  \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return HAB_ERR_DEVICE; \
+    } while (0)
+
+struct Scene {
+    int device = 0;
+    float *pos = nullptr;       // [V][3]
+    uint32_t *col = nullptr;    // [V] packed
+    uint32_t *idx = nullptr;    // [T][3]
+    uint32_t V = 0, T = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    uint64_t bytes = 0;
+};
+
+// One view after validation (host side).
+struct ViewReq {
+    const Scene *scene;
+    hab_sensor sensor;
+    hab_pose pose;
+    uint8_t *rgb;
+    float *depth;
+    uint32_t *tri;
+};
+
+struct PlanOpts {
+    uint32_t tile_size = 0;     // 0: per-class autotuned choice, else default
+    float bin_factor = 0.0f;    // 0: default
+    uint32_t tile_cap = 0;      // 0: unlimited
+};
+
+// Sizes of one launch sequence; used for memory admission as well.
+struct Footprint {
+    uint64_t desc_bytes = 0;    // descriptors copied from the host
+    uint64_t arena_bytes = 0;   // total device scratch incl. descriptors
+};
+
+// Device scratch of one launch sequence plus a ring of pinned staging
+// buffers for the descriptors.  A workspace is used by one launch sequence
+// at a time; `done` orders reuse across streams.
+struct Workspace {
+    int device = 0;
+    void *arena = nullptr;
+    size_t cap = 0;
+    struct Slot {
+        void *host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    static constexpr int kSlots = 4;
+    Slot slots[kSlots];
+    int next = 0;
+    hipEvent_t done = nullptr;
+    bool has_done = false;
+    hipStream_t last_stream = nullptr;
+    bool last_valid = false;
+    // host-side planning buffers, kept to avoid reallocation
+    std::vector<ViewReq> sorted;
+    std::vector<uint32_t> order;
+    std::vector<uint8_t> desc;
+    ~Workspace();
+    hab_status ensure(size_t bytes);
+    hab_status staging(size_t bytes, void **host, int *slot);
+};
+
+// Everything one launch sequence needs, laid out in a workspace arena.
+// Offsets are relative to the arena base; the descriptor block
+// [0, desc_bytes) is copied from pinned host memory before the launch.
+struct Plan {
+    LaunchPlan L{};
+    size_t desc_bytes = 0;
+    size_t arena_bytes = 0;
+    size_t off_views = 0, off_groups = 0, off_lview[3] = {0, 0, 0}, off_lpre[3] = {0, 0, 0};
+    size_t off_ctr = 0, off_tcount = 0, off_toff = 0, off_tcur = 0;
+    size_t off_skey = 0, off_sbox = 0, off_bins = 0;
+    std::vector<uint32_t> order;     // sorted position -> caller index
+    uint32_t n = 0;
+};
+
+struct Tuned {
+    uint32_t key;
+    uint32_t ts;
+    float bin_factor;
+};
+
+}  // namespace habmi
+
+struct hab_context {
+    int device = 0;
+    habmi::Workspace ws;
+    uint32_t *err = nullptr;          // device error word
+    std::vector<habmi::Scene *> scenes;
+    std::vector<habmi::Tuned> tuned;  // autotune table
+    std::mutex tune_mu;
+    int cu_count = 256;
+};
+
+struct hab_scene : habmi::Scene {};
+
+namespace habmi {
+
+hab_status validate_sensor(const hab_sensor *s);
+hab_status validate_pose(const Scene *sc, const hab_sensor *s, const hab_pose *p);
+uint32_t class_key(const Scene *sc, const hab_sensor *s);
+uint32_t choose_tile(hab_context *ctx, const Scene *sc, const hab_sensor *s, const PlanOpts &o,
+                     float *bin_factor);
+// Lay out a plan for views [0, n) (validated) in workspace-relative offsets.
+hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
+                      const PlanOpts &o, Plan &plan, std::vector<uint8_t> &desc);
+// Bind a plan to an arena base address.
+void bind_plan(Plan &plan, void *arena, uint32_t *err);
+// Plan, stage and enqueue one launch sequence on stream s (n <= kMaxViews,
+// footprint checked by the caller).  If stats != NULL, synchronises and
+// fills them (caller order).
+hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
+                        const PlanOpts &o, hipStream_t s, hab_view_stats *stats);
+// Split a request list into launch sequences that fit the limits and run
+// them all.
+hab_status render_all(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
+                      const PlanOpts &o, hipStream_t s, hab_view_stats *stats);
+Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context *ctx);
+hab_status to_view_req(const hab_view &hv, ViewReq &out);
+
+}  // namespace habmi

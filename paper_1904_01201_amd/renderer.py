@@ -1,0 +1,249 @@
+"""Python front end of the renderer: a context with resident scenes,
+sensors, per-view / batched rendering, a graph-captured stepper, a serving
+loop and the autotuner.  Thin wrappers over the C ABI (include/hab.h)."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import binding as B
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(int(t.data_ptr()))
+
+
+_DT = {"rgb": "uint8", "depth": "float32", "tri": ("int32", "uint32")}
+
+
+def check_output(name, t, n, sensor):
+    """Refuse an output tensor that is not a contiguous CUDA tensor of the
+    exact size the library will write ([n, H, W, 3] uint8, [n, H, W] float32
+    or [n, H, W] int32)."""
+    if t is None:
+        return
+    torch = _torch()
+    H, W = int(sensor.height), int(sensor.width)
+    want = n * H * W * (3 if name == "rgb" else 1)
+    dt = str(t.dtype).replace("torch.", "")
+    ok_dt = _DT[name] if isinstance(_DT[name], tuple) else (_DT[name],)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA tensor")
+    if dt not in ok_dt:
+        raise ValueError(f"{name}: dtype {dt}, expected {ok_dt[0]}")
+    if not t.is_contiguous() or t.numel() != want:
+        raise ValueError(f"{name}: need a contiguous tensor of {want} elements, got {tuple(t.shape)}")
+
+
+@dataclass
+class SceneHandle:
+    ptr: int
+    num_vertices: int
+    num_triangles: int
+    device_bytes: int
+    lo: tuple
+    hi: tuple
+
+
+class Context:
+    """One device context (scenes stay resident in HBM until released)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = B.load()
+        self.device = device
+        h = C.c_void_p()
+        B.check(self.lib.hab_init(device, C.byref(h)), "hab_init")
+        self.h = h
+        self._scenes = []
+
+    def close(self):
+        if self.h:
+            B.check(self.lib.hab_shutdown(self.h), "hab_shutdown")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------ scenes
+    def upload(self, positions, colors, indices, stream=None) -> SceneHandle:
+        pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
+        idx = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
+        col = None if colors is None else np.ascontiguousarray(colors, np.uint8).reshape(-1, 3)
+        d = B.MeshDesc(pos.ctypes.data, pos.shape[0], None if col is None else col.ctypes.data,
+                       idx.ctypes.data if idx.size else None, idx.shape[0])
+        out = C.c_void_p()
+        B.check(self.lib.hab_scene_upload(self.h, C.byref(d), _stream_ptr(stream), C.byref(out)),
+                "hab_scene_upload")
+        nv, nt, nb = C.c_uint32(), C.c_uint32(), C.c_uint64()
+        lo, hi = (C.c_float * 3)(), (C.c_float * 3)()
+        B.check(self.lib.hab_scene_info(out, C.byref(nv), C.byref(nt), C.byref(nb), lo, hi))
+        s = SceneHandle(out.value, nv.value, nt.value, nb.value, tuple(lo), tuple(hi))
+        self._scenes.append(s)
+        return s
+
+    def upload_scene(self, scene, stream=None) -> SceneHandle:
+        return self.upload(scene.positions, scene.colors, scene.indices, stream)
+
+    def release(self, scene: SceneHandle):
+        B.check(self.lib.hab_scene_release(self.h, C.c_void_p(scene.ptr)), "hab_scene_release")
+        self._scenes.remove(scene)
+
+    # ------------------------------------------------------------ sensors
+    @staticmethod
+    def sensor(width, height, hfov_deg=90.0, near_m=0.01, outputs=B.OUT_RGB | B.OUT_DEPTH) -> B.Sensor:
+        lib = B.load()
+        d = B.SensorDesc(int(width), int(height), float(hfov_deg), float(near_m), int(outputs))
+        s = B.Sensor()
+        B.check(lib.hab_sensor_spec(C.byref(d), C.byref(s)), "hab_sensor_spec")
+        return s
+
+    # ------------------------------------------------------------ outputs
+    @staticmethod
+    def alloc(sensor: B.Sensor, n: int, tri: bool = False, device="cuda"):
+        torch = _torch()
+        H, W = sensor.height, sensor.width
+        out = {}
+        if sensor.outputs & B.OUT_RGB:
+            out["rgb"] = torch.empty((n, H, W, 3), dtype=torch.uint8, device=device)
+        if sensor.outputs & B.OUT_DEPTH:
+            out["depth"] = torch.empty((n, H, W), dtype=torch.float32, device=device)
+        if tri or (sensor.outputs & B.OUT_TRI):
+            out["tri"] = torch.empty((n, H, W), dtype=torch.int32, device=device)
+        return out
+
+    @staticmethod
+    def _opts(tile_size=0, bin_factor=0.0, tile_cap=0, stats=None):
+        o = B.RenderOpts(int(tile_size), float(bin_factor), int(tile_cap), None)
+        if stats is not None:
+            o.stats = C.cast(stats, C.POINTER(B.ViewStats))
+        return o
+
+    # ------------------------------------------------------------ render
+    def render(self, scene: SceneHandle, sensor: B.Sensor, poses, rgb=None, depth=None, tri=None,
+               tile_size=0, bin_factor=0.0, tile_cap=0, stats=False, stream=None, out=None):
+        """Render N views of one scene.  Returns dict of output tensors (and
+        'stats': list of dicts if requested)."""
+        poses = np.asarray(poses, np.float32).reshape(-1, 12)
+        n = poses.shape[0]
+        if out is None:
+            out = {}
+        if rgb is not None:
+            out["rgb"] = rgb
+        if depth is not None:
+            out["depth"] = depth
+        if tri is not None:
+            out["tri"] = tri
+        if not out:
+            out = self.alloc(sensor, n, tri=False)
+        for k in ("rgb", "depth", "tri"):
+            check_output(k, out.get(k), n, sensor)
+        st = (B.ViewStats * n)() if stats else None
+        o = self._opts(tile_size, bin_factor, tile_cap, st)
+        pc = B.poses_to_c(poses)
+        B.check(self.lib.hab_render_ex(self.h, C.c_void_p(scene.ptr), C.byref(sensor), pc, n,
+                                       _ptr(out.get("rgb")), _ptr(out.get("depth")),
+                                       _ptr(out.get("tri")), C.byref(o), _stream_ptr(stream)),
+                "hab_render_ex")
+        if stats:
+            out["stats"] = [{"survivors": s.survivors, "bbox_tests": s.bbox_tests,
+                             "covered": s.covered} for s in st]
+        return out
+
+    def render_plain(self, scene, sensor, poses, rgb=None, depth=None, stream=None):
+        """hab_render: the minimal entry point."""
+        poses = np.asarray(poses, np.float32).reshape(-1, 12)
+        check_output("rgb", rgb, poses.shape[0], sensor)
+        check_output("depth", depth, poses.shape[0], sensor)
+        pc = B.poses_to_c(poses)
+        B.check(self.lib.hab_render(self.h, C.c_void_p(scene.ptr), C.byref(sensor), pc,
+                                    poses.shape[0], _ptr(rgb), _ptr(depth), _stream_ptr(stream)),
+                "hab_render")
+
+    def make_views(self, items):
+        """items: iterable of (scene, sensor, pose, rgb, depth, tri) with
+        tensors or None.  Returns a ctypes View array (keeps sensors alive)."""
+        items = list(items)
+        arr = (B.View * len(items))()
+        keep = []
+        for k, (scene, sensor, pose, rgb, depth, tri) in enumerate(items):
+            check_output("rgb", rgb, 1, sensor)
+            check_output("depth", depth, 1, sensor)
+            check_output("tri", tri, 1, sensor)
+            keep.append(sensor)
+            arr[k].scene = scene.ptr
+            arr[k].sensor = C.pointer(sensor)
+            arr[k].pose = B.pose_to_c(pose)
+            arr[k].out_rgb = None if rgb is None else int(rgb.data_ptr())
+            arr[k].out_depth = None if depth is None else int(depth.data_ptr())
+            arr[k].out_tri = None if tri is None else int(tri.data_ptr())
+        arr._keep = keep
+        return arr
+
+    def render_batch(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stats=False, stream=None,
+                     views=None):
+        arr = views if views is not None else self.make_views(items)
+        n = len(arr)
+        st = (B.ViewStats * n)() if stats else None
+        o = self._opts(tile_size, bin_factor, tile_cap, st)
+        B.check(self.lib.hab_render_batch(self.h, arr, n, C.byref(o), _stream_ptr(stream)),
+                "hab_render_batch")
+        if stats:
+            return [{"survivors": s.survivors, "bbox_tests": s.bbox_tests, "covered": s.covered}
+                    for s in st]
+        return None
+
+    def get_error(self) -> int:
+        return int(self.lib.hab_get_error(self.h))
+
+    # ------------------------------------------------------------ stepper
+    def stepper(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None):
+        return Stepper(self, items, tile_size, bin_factor, tile_cap, stream)
+
+    # ------------------------------------------------------------ autotune
+    def autotune(self, items, stream=None):
+        arr = self.make_views(items)
+        ts, bf = C.c_uint32(), C.c_float()
+        B.check(self.lib.hab_autotune(self.h, arr, len(arr), _stream_ptr(stream), C.byref(ts),
+                                      C.byref(bf)), "hab_autotune")
+        return int(ts.value), float(bf.value)
+
+
+class Stepper:
+    """A fixed batch composition captured as a HIP graph; step(poses)."""
+
+    def __init__(self, ctx: Context, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None):
+        self.ctx = ctx
+        self.views = ctx.make_views(items)
+        o = Context._opts(tile_size, bin_factor, tile_cap)
+        h = C.c_void_p()
+        B.check(ctx.lib.hab_stepper_create(ctx.h, self.views, len(self.views), C.byref(o),
+                                           _stream_ptr(stream), C.byref(h)), "hab_stepper_create")
+        self.h = h
+
+    def step(self, poses, stream=None):
+        pc = B.poses_to_c(poses)
+        if len(pc) != len(self.views):
+            raise ValueError("one pose per view")
+        B.check(self.ctx.lib.hab_stepper_step(self.h, pc, _stream_ptr(stream)), "hab_stepper_step")
+
+    def close(self):
+        if self.h:
+            B.check(self.ctx.lib.hab_stepper_destroy(self.h), "hab_stepper_destroy")
+            self.h = None

@@ -1,0 +1,82 @@
+"""Host-only checks of the C ABI (no GPU needed): the built library loads,
+exports every function include/hab.h declares, validates sensor requests
+and reports status strings."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1904_01201_amd as P
+from paper_1904_01201_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hab.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:hab_status|const char \*)\s*(hab_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.lib_path()):
+        pytest.fail("libhabmi.so is not built (run __graft_entry__.build())")
+    return B.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(B.EXPORTED) == set(names)
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert lib.hab_status_string(s)
+    assert lib.hab_status_string(99) == b"unknown status"
+
+
+def spec(w, h, hfov=90.0, near=0.0, outputs=0):
+    d = B.SensorDesc(w, h, hfov, near, outputs)
+    s = B.Sensor()
+    rc = B.load().hab_sensor_spec(C.byref(d), C.byref(s))
+    return rc, s
+
+
+def test_sensor_spec_paper_defaults(lib):
+    """256^2 at 90 degrees: f = 128 exactly; defaults near 0.01 and RGB+D."""
+    rc, s = spec(256, 256)
+    assert rc == B.HAB_OK
+    assert s.f == 128.0 and abs(s.near_m - 0.01) < 1e-9 and s.outputs == 3
+
+
+@pytest.mark.parametrize("args", [(0, 16), (16, 0), (4097, 16), (16, 16, 0.0), (16, 16, 180.0),
+                                  (16, 16, 90.0, -1.0), (16, 16, 90.0, 0.0, 8),
+                                  (16, 16, float("nan"))])
+def test_sensor_spec_rejects(lib, args):
+    rc, _ = spec(*args)
+    assert rc == B.HAB_ERR_INVALID_ARG
+
+
+def test_null_arguments(lib):
+    assert lib.hab_init(0, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_shutdown(None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_get_error(None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_render(None, None, None, None, 0, None, None, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_render_batch(None, None, 0, None, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_stepper_step(None, None, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_server_submit(None, None, None) == B.HAB_ERR_INVALID_ARG
+
+
+def test_output_tensor_checks():
+    """The binding refuses output buffers of the wrong size before calling
+    into the library (a short buffer would be written out of bounds)."""
+    torch = pytest.importorskip("torch")
+    from paper_1904_01201_amd.renderer import check_output
+    s = B.Sensor(8, 4, 3, 90.0, 4.0, 0.01)
+    with pytest.raises(ValueError):
+        check_output("depth", torch.empty(31), 1, s)      # CPU tensor / wrong size
