@@ -243,6 +243,22 @@ hab_status hab_server_stats_get(hab_server *srv, hab_server_stats *out);
 /* Drain outstanding work, stop the loop, free server resources. */
 hab_status hab_server_destroy(hab_server *srv);
 
+/* ---------------------------------------------------------- profiling */
+/* Per-phase device time, from HIP events recorded on the launch stream
+ * around every kernel while profiling is on (hab_profile_enable).  Phases:
+ * 0 reset, 1 setup, 2 bin count, 3 bin scan, 4 bin scatter, 5..7 raster
+ * with tile size 8, 16, 32, 8 resolve.  Graph replays (stepper) are not
+ * timed. */
+#define HAB_NUM_PHASES 9
+typedef struct {
+    double ms[HAB_NUM_PHASES];        /* summed device time per phase        */
+    uint64_t launches[HAB_NUM_PHASES]; /* kernel launches per phase           */
+    uint64_t sequences;                /* launch sequences that were timed    */
+} hab_phase_times;
+hab_status hab_profile_enable(hab_context *ctx, int on);
+/* Synchronise, add up every timed sequence since the last read, reset. */
+hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out);
+
 /* ---------------------------------------------------------- autotune */
 /* Time the candidate tile sizes and bin capacities on a sample batch and
  * remember the fastest for this batch class (scene size, resolution,

@@ -33,7 +33,10 @@ EXPORTED = [
     "hab_stepper_create", "hab_stepper_step", "hab_stepper_destroy",
     "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
+    "hab_profile_enable", "hab_profile_read",
 ]
+PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "raster16",
+          "raster32", "resolve"]
 
 
 class MeshDesc(C.Structure):
@@ -84,6 +87,10 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("batches", C.c_uint64),
                 ("rejected", C.c_uint64), ("peak_inflight_bytes", C.c_uint64),
                 ("peak_batch", C.c_uint32)]
+
+
+class PhaseTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 9), ("launches", C.c_uint64 * 9), ("sequences", C.c_uint64)]
 
 
 class HabError(RuntimeError):
@@ -139,6 +146,8 @@ def load():
             "hab_server_stats_get": [vp, C.POINTER(ServerStats)],
             "hab_server_destroy": [vp],
             "hab_autotune": [vp, C.POINTER(View), u32, vp, C.POINTER(u32), C.POINTER(f32)],
+            "hab_profile_enable": [vp, C.c_int],
+            "hab_profile_read": [vp, C.POINTER(PhaseTimes)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)

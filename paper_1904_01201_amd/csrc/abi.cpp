@@ -73,6 +73,7 @@ hab_status hab_init(int device, hab_context **out)
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
             ctx->cu_count = prop.multiProcessorCount;
+        for (int c = 0; c < 3; ++c) ctx->raster_bpc[c] = raster_blocks_per_cu(8 << c);
         if (hipMalloc(&ctx->err, 256) != hipSuccess) {
             (void)hipGetLastError();
             delete ctx;
@@ -101,6 +102,8 @@ hab_status hab_shutdown(hab_context *ctx)
             delete static_cast<hab_scene *>(s);
         }
         ctx->scenes.clear();
+        for (auto &ps : ctx->prof_sets)
+            for (auto &e : ps.ev) (void)hipEventDestroy(e);
         if (ctx->err) (void)hipFree(ctx->err);
         delete ctx;
         return HAB_OK;
@@ -320,6 +323,36 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t n,
         DeviceGuard g(ctx->device);
         if (!g.ok) return HAB_ERR_DEVICE;
         return render_all(ctx, ctx->ws, req.data(), n, o, stream, opts ? opts->stats : nullptr);
+    });
+}
+
+hab_status hab_profile_enable(hab_context *ctx, int on)
+{
+    if (!ctx) return HAB_ERR_INVALID_ARG;
+    ctx->prof_on = on != 0;
+    return HAB_OK;
+}
+
+hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out)
+{
+    if (!ctx || !out) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        DeviceGuard g(ctx->device);
+        std::memset(out, 0, sizeof *out);
+        for (size_t k = 0; k < ctx->prof_used; ++k) {
+            const hab_context::ProfSet &ps = ctx->prof_sets[k];
+            for (int ph = 0; ph < HAB_NUM_PHASES; ++ph) {
+                if (!(ps.mask & (1u << ph))) continue;
+                HAB_HIP(hipEventSynchronize(ps.ev[2 * ph + 1]));
+                float ms = 0.0f;
+                HAB_HIP(hipEventElapsedTime(&ms, ps.ev[2 * ph], ps.ev[2 * ph + 1]));
+                out->ms[ph] += ms;
+                out->launches[ph] += 1;
+            }
+        }
+        out->sequences = ctx->prof_used;
+        ctx->prof_used = 0;
+        return HAB_OK;
     });
 }
 

@@ -49,6 +49,13 @@ struct DGroup {
     uint32_t block_start;       // first setup block of this group
 };
 
+// Work queues of the raster stage, one per tile size (8, 16, 32): `total`
+// items were appended by the scan, `head` is the next one to hand out.
+struct DQueue {
+    uint32_t head[4];
+    uint32_t total[4];
+};
+
 // Per-view counters (zeroed at the start of every launch sequence).
 struct DViewCounters {
     uint32_t surv_count;        // survivors appended by setup

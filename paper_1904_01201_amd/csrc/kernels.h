@@ -8,14 +8,21 @@
 namespace habmi {
 
 constexpr uint32_t kMaxViews = 4096;   // views per launch sequence
+constexpr uint32_t kSegPerTile = 4;    // a work item covers <= 4 * TS^2 list entries
+constexpr uint32_t kMaxSegments = 1u << 14;
 
-// One raster launch: all views of a batch that use the same tile size.
+// One raster + resolve launch pair: all views of a batch that use the same
+// tile size.
 struct RasterLaunch {
     int ts;                    // 8, 16 or 32
-    const uint32_t *lview;     // [nl] view index
+    const uint32_t *lview;     // [nl] view index (resolve: block -> view)
     const uint32_t *lpre;      // [nl] first block of each view (prefix of tile counts)
     uint32_t nl;
-    uint32_t blocks;           // total tiles
+    uint32_t blocks;           // total tiles (resolve grid)
+    uint32_t grid;             // persistent raster blocks
+    uint64_t item_cap;         // work items the scratch below can hold
+    uint2 *items;              // [item_cap] (view, tile | segment << 18)
+    uint2 *partial;            // [item_cap][TS*TS] per-pixel (1/w bits, key) of each item
 };
 
 // Device pointers and sizes of one launch sequence.
@@ -33,11 +40,22 @@ struct LaunchPlan {
     uint32_t *tile_cursor;
     uint32_t ntiles;
     uint32_t *bins;
+    uint32_t *tile_item;       // first work item of each tile
+    DQueue *queue;
+    uint2 *items[3];           // per tile size (null when unused)
     uint32_t *err;
     uint32_t bin_grid;
     RasterLaunch raster[3];
     int nraster;
+    hipEvent_t *prof;          // null, or kProfEvents events recorded around the kernels
 };
+
+constexpr int kPhaseResolve = 8;
+constexpr int kProfPhases = 9;
+constexpr int kProfEvents = 2 * kProfPhases;   // start/stop per phase
+
+// Resident k_raster<ts> blocks per compute unit (sizes the persistent grid).
+int raster_blocks_per_cu(int ts);
 
 // Enqueue the whole sequence on stream s.
 hipError_t launch_render(const LaunchPlan &L, hipStream_t s);

@@ -2,26 +2,31 @@
 //
 // One launch sequence renders a batch of views (any mix of scenes,
 // resolutions and output sets):
-//   k_reset      zero the per-view counters and per-tile counters
+//   k_reset      zero the per-view, per-tile and work-queue counters
 //   k_setup      per (scene group, triangle): fetch the triangle once, then
 //                for every view of the group transform, clip, snap, orient
 //                and cull; survivors (key, pixel bbox) are appended to the
 //                view's list with wave-level prefix-sum compaction
-//   k_bin_count  per survivor, count the screen tiles its bbox touches
-//                (wave-aggregated atomics)
-//   k_bin_scan   per view, exclusive scan of the tile counts into list
-//                offsets; tiles over capacity are marked for the overflow
-//                path (lossless)
-//   k_bin_scatter per survivor, write its key into each touched tile list
-//   k_raster<TS> per (view, tile): stage the tile's triangles through LDS
-//                (each lane rebuilds one triangle's edge setup relative to
-//                the tile), then every lane owns one pixel and keeps the
-//                nearest (largest 1/w, smaller key on ties) in registers:
-//                an atomic-free z-test that does not depend on list order;
-//                finally the winner is resolved to colour, depth and index.
-// The arithmetic that decides coverage and visibility is exact integer
-// (edge functions) or one fixed sequence of fp32 operations (the key), so
-// the output is the same for every batching, tile size and capacity.
+//   k_bin<count> per chunk of survivors: LDS histogram of the screen tiles
+//                their boxes touch, one global add per touched tile
+//   k_bin_scan   per view: exclusive scans of the tile counts (list offsets;
+//                tiles over capacity take the lossless overflow path) and of
+//                the tiles' segment counts; the (tile, segment) work items
+//                are appended to the queue of the view's tile size
+//   k_bin<scatter> per chunk of survivors: write each key into every touched
+//                tile's list (LDS ranks, one global reservation per tile)
+//   k_raster<TS> persistent blocks pull (tile, segment) items from the queue
+//                (an atomic counter used for work distribution only).  The
+//                segment's triangles are staged through LDS (each lane
+//                rebuilds one edge setup relative to the tile), then every
+//                lane owns one pixel and keeps the nearest candidate (largest
+//                1/w, smaller key on ties) in registers: an atomic-free
+//                z-test; the segment's per-pixel winner goes to scratch
+//   k_resolve<TS> per tile: merge the segments' winners with the same rule,
+//                rebuild the winner, write colour, planar depth and index.
+// Coverage and visibility are decided by exact integer edge functions and
+// one fixed sequence of fp32 operations (the key), so outputs do not depend
+// on batching, tile size, capacity, segmenting or scheduling order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -74,10 +79,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot, 
     return pre + s - x;
 }
 
-// Add `inc` to counters[key] for every lane with `has`, one atomic per
-// distinct key in the wave.  Returns, per participating lane, the value
-// the counter had before the wave's additions plus the lane's rank among
-// the lanes with the same key (i.e. a unique slot when inc == 1).
+// Add 1 to counters[key] for every lane with `has`, one atomic per distinct
+// key in the wave.  Returns, per participating lane, the counter's value
+// before the wave's additions plus the lane's rank among the lanes with the
+// same key: a unique slot.
 __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *counters, uint32_t key, bool has)
 {
     unsigned long long pending = __ballot(has);
@@ -119,7 +124,8 @@ __device__ __forceinline__ void load_tri(const DView &v, uint32_t t, float P[9],
 // ------------------------------------------------------------ k_reset
 __global__ __launch_bounds__(256) void k_reset(DViewCounters *__restrict__ ctr, uint32_t nviews,
                                                uint32_t *__restrict__ tile_count,
-                                               uint32_t *__restrict__ tile_cursor, uint32_t ntiles)
+                                               uint32_t *__restrict__ tile_cursor, uint32_t ntiles,
+                                               DQueue *__restrict__ q)
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i < nviews) {
@@ -132,9 +138,55 @@ __global__ __launch_bounds__(256) void k_reset(DViewCounters *__restrict__ ctr, 
         tile_count[i] = 0;
         tile_cursor[i] = 0;
     }
+    if (i < 4) {
+        q->head[i] = 0;
+        q->total[i] = 0;
+    }
 }
 
 // ------------------------------------------------------------ k_setup
+// Survival of sub-triangles 0 and 1 of one triangle in view v, with their
+// pixel boxes.  Deterministic: calling it twice gives the same answer.
+__device__ __forceinline__ void survive(const DView &v, const float P[9], bool valid, bool &s0,
+                                        bool &s1, PixBox &b0, PixBox &b1, bool &rerr)
+{
+    s0 = s1 = false;
+    if (!valid) return;
+    Vtx<0> c0, c1, c2;
+    cam_xform(v, P[0], P[1], P[2], c0);
+    cam_xform(v, P[3], P[4], P[5], c1);
+    cam_xform(v, P[6], P[7], P[8], c2);
+    const float zn = v.zn;
+    const bool allin = c0.w >= zn && c1.w >= zn && c2.w >= zn;
+    const bool anyin = c0.w >= zn || c1.w >= zn || c2.w >= zn;
+    if (!anyin) return;
+    if (allin) {
+        // Conservative frustum rejection before any division: if all three
+        // |Xc fS| exceed (cxS + 4 px)(1 + 2^-16) w on one side, the snapped
+        // bbox is at least 3 px outside the viewport (three fp32 roundings
+        // cost < 2^-22 relative), so the exact path would cull it too.
+        const float Kx = (v.cxS + 1024.0f) * 1.0000152587890625f;
+        const float Ky = (v.cyS + 1024.0f) * 1.0000152587890625f;
+        const float x0 = c0.x * v.fS, x1 = c1.x * v.fS, x2 = c2.x * v.fS;
+        const float y0 = c0.y * v.fS, y1 = c1.y * v.fS, y2 = c2.y * v.fS;
+        const float kx0 = Kx * c0.w, kx1 = Kx * c1.w, kx2 = Kx * c2.w;
+        const float ky0 = Ky * c0.w, ky1 = Ky * c1.w, ky2 = Ky * c2.w;
+        if ((x0 > kx0 && x1 > kx1 && x2 > kx2) || (x0 < -kx0 && x1 < -kx1 && x2 < -kx2) ||
+            (y0 > ky0 && y1 > ky1 && y2 > ky2) || (y0 < -ky0 && y1 < -ky1 && y2 < -ky2))
+            return;
+    }
+    SVtx<0> a, bb, c;
+    long long A;
+    if (setup_sub(v, c0, c1, c2, 0, a, bb, c, A, rerr)) {
+        b0 = pix_box(v, a, bb, c);
+        s0 = b0.i0 <= b0.i1 && b0.j0 <= b0.j1;
+    }
+    if (!allin && setup_sub(v, c0, c1, c2, 1, a, bb, c, A, rerr)) {
+        b1 = pix_box(v, a, bb, c);
+        s1 = b1.i0 <= b1.i1 && b1.j0 <= b1.j1;
+    }
+}
+
 __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__ views,
                                                        const DGroup *__restrict__ groups,
                                                        int ngroups, DViewCounters *__restrict__ ctr,
@@ -163,67 +215,54 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
     }
     const uint32_t lane = lane_id();
     const unsigned long long lt = lanemask_lt();
+    const uint32_t nv = G.num_views;   // <= 16: two survival bits per view fit one word
     bool rerr = false;
 
-    for (uint32_t k = 0; k < G.num_views; ++k) {
-        const uint32_t vi = G.first_view + k;
-        const DView &v = views[vi];
-        Vtx<0> c0, c1, c2;
-        cam_xform(v, P[0], P[1], P[2], c0);
-        cam_xform(v, P[3], P[4], P[5], c1);
-        cam_xform(v, P[6], P[7], P[8], c2);
-        bool s0 = false, s1 = false;
-        PixBox b0 = {0, -1, 0, -1}, b1 = {0, -1, 0, -1};
-        if (valid) {
-            const float zn = v.zn;
-            const bool allin = c0.w >= zn && c1.w >= zn && c2.w >= zn;
-            const bool anyin = c0.w >= zn || c1.w >= zn || c2.w >= zn;
-            bool cull = !anyin;
-            if (allin) {
-                // Conservative frustum rejection before any division: if all
-                // three |Xc fS| exceed (cxS + 4 px)(1 + 2^-16) w on one side,
-                // the snapped bbox is at least 3 px outside the viewport
-                // (three fp32 roundings cost < 2^-22 relative), so the exact
-                // path would cull it too.
-                const float Kx = (v.cxS + 1024.0f) * 1.0000152587890625f;
-                const float Ky = (v.cyS + 1024.0f) * 1.0000152587890625f;
-                const float x0 = c0.x * v.fS, x1 = c1.x * v.fS, x2 = c2.x * v.fS;
-                const float y0 = c0.y * v.fS, y1 = c1.y * v.fS, y2 = c2.y * v.fS;
-                const float kx0 = Kx * c0.w, kx1 = Kx * c1.w, kx2 = Kx * c2.w;
-                const float ky0 = Ky * c0.w, ky1 = Ky * c1.w, ky2 = Ky * c2.w;
-                cull = (x0 > kx0 && x1 > kx1 && x2 > kx2) || (x0 < -kx0 && x1 < -kx1 && x2 < -kx2) ||
-                       (y0 > ky0 && y1 > ky1 && y2 > ky2) || (y0 < -ky0 && y1 < -ky1 && y2 < -ky2);
-            }
-            if (!cull) {
-                SVtx<0> a, bb, c;
-                long long A;
-                if (setup_sub(v, c0, c1, c2, 0, a, bb, c, A, rerr)) {
-                    b0 = pix_box(v, a, bb, c);
-                    s0 = b0.i0 <= b0.i1 && b0.j0 <= b0.j1;
-                }
-                if (!allin && setup_sub(v, c0, c1, c2, 1, a, bb, c, A, rerr)) {
-                    b1 = pix_box(v, a, bb, c);
-                    s1 = b1.i0 <= b1.i1 && b1.j0 <= b1.j1;
-                }
-            }
-        }
+    // pass 1: which sub-triangles survive in which view; lane k collects
+    // the wave's totals for view k
+    uint32_t bits = 0, totv = 0, alov = 0, ahiv = 0;
+    for (uint32_t k = 0; k < nv; ++k) {
+        const DView &v = views[G.first_view + k];
+        bool s0, s1;
+        PixBox b0, b1;
+        survive(v, P, valid, s0, s1, b0, b1, rerr);
+        bits |= (s0 ? 1u : 0u) << (2 * k);
+        bits |= (s1 ? 1u : 0u) << (2 * k + 1);
         const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
         if (m0 | m1) {
-            const uint32_t tot = (uint32_t)(__popcll(m0) + __popcll(m1));
-            const uint32_t pre = (uint32_t)(__popcll(m0 & lt) + __popcll(m1 & lt));
             uint32_t area = 0;
             if (s0) area += (uint32_t)(b0.i1 - b0.i0 + 1) * (uint32_t)(b0.j1 - b0.j0 + 1);
             if (s1) area += (uint32_t)(b1.i1 - b1.i0 + 1) * (uint32_t)(b1.j1 - b1.j0 + 1);
-            // two boxes per lane of at most 2^24 pixels each: the wave sum
-            // of the low and high halves cannot overflow separately
+            // two boxes of at most 2^24 pixels per lane: the two halves of
+            // the wave sum cannot overflow
             const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
             const uint32_t ahi = wave_sum_u32(area >> 16);
-            uint32_t base = 0;
-            if (lane == 0) {
-                base = atomicAdd(&ctr[vi].surv_count, tot);
-                atomicAdd(&ctr[vi].bbox_tests, (unsigned long long)alo + ((unsigned long long)ahi << 16));
+            if (lane == k) {
+                totv = (uint32_t)(__popcll(m0) + __popcll(m1));
+                alov = alo;
+                ahiv = ahi;
             }
-            base = __shfl(base, 0);
+        }
+    }
+    // one atomic round trip for all views of the group (lane k: view k)
+    uint32_t basev = 0;
+    if (lane < nv && totv) {
+        basev = atomicAdd(&ctr[G.first_view + lane].surv_count, totv);
+        atomicAdd(&ctr[G.first_view + lane].bbox_tests,
+                  (unsigned long long)alov + ((unsigned long long)ahiv << 16));
+    }
+    // pass 2: rebuild the surviving boxes and write them at their slots
+    for (uint32_t k = 0; k < nv; ++k) {
+        const uint32_t tot = __shfl(totv, (int)k);
+        if (!tot) continue;
+        const uint32_t base = __shfl(basev, (int)k);
+        const bool s0 = (bits >> (2 * k)) & 1u, s1 = (bits >> (2 * k + 1)) & 1u;
+        const uint32_t pre = (uint32_t)(__popcll(__ballot(s0) & lt) + __popcll(__ballot(s1) & lt));
+        if (s0 || s1) {
+            const DView &v = views[G.first_view + k];
+            bool r0, r1;
+            PixBox b0, b1;
+            survive(v, P, valid, r0, r1, b0, b1, rerr);
             uint32_t o = v.surv_base + base + pre;
             if (s0) {
                 skey[o] = 2u * t;
@@ -244,6 +283,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
 // survivors); every block builds the prefix of chunk counts over the views
 // from the device-side survivor counts, then strides over the items.
 constexpr uint32_t kBinChunk = kBinBlock * kBinItems;
+constexpr uint32_t kLdsTiles = 2048;   // views with more tiles bin through global atomics
 
 __device__ __forceinline__ uint32_t build_item_prefix(const DViewCounters *ctr, uint32_t nviews,
                                                       uint32_t *pre, uint32_t *wtot)
@@ -273,6 +313,21 @@ __device__ __forceinline__ uint32_t find_view(const uint32_t *pre, uint32_t nvie
     return lo;
 }
 
+struct TileRange {
+    int tx0, ty0, nx, n;
+};
+
+__device__ __forceinline__ TileRange tile_range(uint2 bb, uint32_t ts)
+{
+    TileRange r;
+    r.tx0 = (int)(bb.x & 0xFFFFu) >> ts;
+    r.ty0 = (int)(bb.x >> 16) >> ts;
+    const int tx1 = (int)(bb.y & 0xFFFFu) >> ts, ty1 = (int)(bb.y >> 16) >> ts;
+    r.nx = tx1 - r.tx0 + 1;
+    r.n = r.nx * (ty1 - r.ty0 + 1);
+    return r;
+}
+
 template <bool SCATTER>
 __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ views, uint32_t nviews,
                                                    const DViewCounters *__restrict__ ctr,
@@ -285,62 +340,125 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
 {
     __shared__ uint32_t pre[kMaxViews];
     __shared__ uint32_t wtot[kBinBlock / 64];
+    __shared__ uint32_t hist[kLdsTiles];   // low 16 bits: count, high 16 bits: rank cursor
+    __shared__ uint32_t lbase[SCATTER ? kLdsTiles : 1];
     const uint32_t total = build_item_prefix(ctr, nviews, pre, wtot);
+    const uint32_t tid = threadIdx.x;
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
         const uint32_t vi = find_view(pre, nviews, item);
         const DView &v = views[vi];
         const uint32_t cnt = ctr[vi].surv_count;
         const uint32_t s0 = (item - pre[vi]) * kBinChunk;
         const uint32_t ts = v.ts_log2;
+        const uint32_t nt = v.tiles_x * v.tiles_y;
+        if (nt <= kLdsTiles) {
+            for (uint32_t i = tid; i < nt; i += kBinBlock) hist[i] = 0;
+            __syncthreads();
+            // count this chunk's entries per tile in LDS (at most kBinChunk
+            // per tile: fits the 16-bit half)
 #pragma unroll 1
-        for (int r = 0; r < kBinItems; ++r) {
-            const uint32_t s = s0 + (uint32_t)r * kBinBlock + threadIdx.x;
-            const bool has = s < cnt;
-            int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
-            uint32_t key = 0;
-            if (has) {
-                const uint2 bb = sbox[v.surv_base + s];
-                tx0 = (int)(bb.x & 0xFFFFu) >> ts;
-                ty0 = (int)(bb.x >> 16) >> ts;
-                tx1 = (int)(bb.y & 0xFFFFu) >> ts;
-                ty1 = (int)(bb.y >> 16) >> ts;
-                if (SCATTER) key = skey[v.surv_base + s];
+            for (int r = 0; r < kBinItems; ++r) {
+                const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
+                if (s >= cnt) break;
+                const TileRange R = tile_range(sbox[v.surv_base + s], ts);
+                for (int k = 0; k < R.n; ++k)
+                    atomicAdd(&hist[(uint32_t)(R.ty0 + k / R.nx) * v.tiles_x + (uint32_t)(R.tx0 + k % R.nx)], 1u);
             }
-            const int nx = tx1 - tx0 + 1;
-            const int n = has ? nx * (ty1 - ty0 + 1) : 0;
-            for (int k = 0; __ballot(k < n); ++k) {
-                bool act = k < n;
-                uint32_t tile = 0;
-                if (act) {
-                    const int ty = ty0 + k / nx, tx = tx0 + k % nx;
-                    tile = v.tile_base + (uint32_t)ty * v.tiles_x + (uint32_t)tx;
-                }
+            __syncthreads();
+            // one global operation per touched tile
+            for (uint32_t i = tid; i < nt; i += kBinBlock) {
+                const uint32_t c = hist[i] & 0xFFFFu;
+                if (!c) continue;
                 if (!SCATTER) {
-                    wave_aggregated_add(tile_count, tile, act);
+                    atomicAdd(&tile_count[v.tile_base + i], c);
                 } else {
-                    const uint32_t off = act ? tile_off[tile] : kOverflow;
-                    act = act && off != kOverflow;
-                    const uint32_t slot = wave_aggregated_add(tile_cursor, tile, act);
-                    if (act) bins[v.bin_base + off + slot] = key;
+                    const uint32_t off = tile_off[v.tile_base + i];
+                    lbase[i] = off == kOverflow ? kOverflow : off + atomicAdd(&tile_cursor[v.tile_base + i], c);
+                }
+            }
+            if (SCATTER) {
+                __syncthreads();
+#pragma unroll 1
+                for (int r = 0; r < kBinItems; ++r) {
+                    const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
+                    if (s >= cnt) break;
+                    const TileRange R = tile_range(sbox[v.surv_base + s], ts);
+                    const uint32_t key = skey[v.surv_base + s];
+                    for (int k = 0; k < R.n; ++k) {
+                        const uint32_t tl = (uint32_t)(R.ty0 + k / R.nx) * v.tiles_x + (uint32_t)(R.tx0 + k % R.nx);
+                        const uint32_t b = lbase[tl];
+                        if (b == kOverflow) continue;
+                        const uint32_t rank = atomicAdd(&hist[tl], 1u << 16) >> 16;
+                        bins[v.bin_base + b + rank] = key;
+                    }
+                }
+            }
+            __syncthreads();
+        } else {
+            // large views: wave-aggregated global atomics
+#pragma unroll 1
+            for (int r = 0; r < kBinItems; ++r) {
+                const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
+                const bool has = s < cnt;
+                TileRange R = {0, 0, 1, 0};
+                uint32_t key = 0;
+                if (has) {
+                    R = tile_range(sbox[v.surv_base + s], ts);
+                    if (SCATTER) key = skey[v.surv_base + s];
+                }
+                for (int k = 0; __ballot(k < R.n); ++k) {
+                    bool act = k < R.n;
+                    uint32_t tile = 0;
+                    if (act) tile = v.tile_base + (uint32_t)(R.ty0 + k / R.nx) * v.tiles_x + (uint32_t)(R.tx0 + k % R.nx);
+                    if (!SCATTER) {
+                        wave_aggregated_add(tile_count, tile, act);
+                    } else {
+                        const uint32_t off = act ? tile_off[tile] : kOverflow;
+                        act = act && off != kOverflow;
+                        const uint32_t slot = wave_aggregated_add(tile_cursor, tile, act);
+                        if (act) bins[v.bin_base + off + slot] = key;
+                    }
                 }
             }
         }
     }
 }
 
+__device__ __forceinline__ uint32_t seg_size(uint32_t ts_log2) { return kSegPerTile << (2 * ts_log2); }
+
+// Number of (tile, segment) work items of a tile: none when empty, one for
+// an overflow tile (it scans the whole survivor list), else one per
+// segment of at most kSegPerTile * TS^2 list entries.
+__device__ __forceinline__ uint32_t tile_segments(uint32_t c, uint32_t off, uint32_t ts_log2)
+{
+    if (c == 0) return 0;
+    if (off == kOverflow) return 1;
+    const uint32_t S = seg_size(ts_log2);
+    return (c + S - 1) / S;
+}
+
 // Per view: exclusive scan of tile counts into list offsets.  A tile whose
 // count exceeds tile_cap, or whose list would end beyond the view's bin
-// capacity, is marked kOverflow and rasterised from the full survivor list.
+// capacity, is marked kOverflow.  Then the view's work items are reserved
+// in its tile size's queue and written out; tile_item gets each tile's
+// first item.
 __global__ __launch_bounds__(kScanBlock) void k_bin_scan(const DView *__restrict__ views,
                                                          DViewCounters *__restrict__ ctr,
                                                          const uint32_t *__restrict__ tile_count,
-                                                         uint32_t *__restrict__ tile_off)
+                                                         uint32_t *__restrict__ tile_off,
+                                                         uint32_t *__restrict__ tile_item,
+                                                         DQueue *__restrict__ q,
+                                                         uint2 *__restrict__ items8,
+                                                         uint2 *__restrict__ items16,
+                                                         uint2 *__restrict__ items32)
 {
     __shared__ uint32_t wtot[kScanBlock / 64];
+    __shared__ uint32_t sbase;
     const uint32_t vi = blockIdx.x;
     const DView &v = views[vi];
     const uint32_t n = v.tiles_x * v.tiles_y;
-    uint32_t run = 0;
+    const uint32_t cls = v.ts_log2 - 3;
+    uint32_t run = 0, srun = 0;
     for (uint32_t base = 0; base < n; base += kScanBlock) {
         const uint32_t i = base + threadIdx.x;
         const uint32_t c = i < n ? tile_count[v.tile_base + i] : 0u;
@@ -348,43 +466,61 @@ __global__ __launch_bounds__(kScanBlock) void k_bin_scan(const DView *__restrict
         uint32_t tot;
         const uint32_t ex = block_excl_scan<kScanBlock>(e, wtot, &tot);
         const unsigned long long P = (unsigned long long)run + ex;
+        // a tile with more segments than the item encoding holds also takes
+        // the (single-item) overflow path
+        const bool over = c > v.tile_cap || P + e > v.bin_cap ||
+                          c > (kMaxSegments - 1) * seg_size(v.ts_log2);
+        const uint32_t off = (c == 0) ? 0u : (over ? kOverflow : (uint32_t)P);
+        const uint32_t ns = tile_segments(c, off, v.ts_log2);
+        uint32_t stot;
+        const uint32_t sex = block_excl_scan<kScanBlock>(ns, wtot, &stot);
         if (i < n) {
-            const bool over = c > v.tile_cap || P + e > v.bin_cap;
-            tile_off[v.tile_base + i] = (c == 0) ? 0u : (over ? kOverflow : (uint32_t)P);
+            tile_off[v.tile_base + i] = off;
+            tile_item[v.tile_base + i] = srun + sex;
         }
         run += tot;
+        srun += stot;
     }
-    if (threadIdx.x == 0) ctr[vi].bin_used = min(run, v.bin_cap);
+    if (threadIdx.x == 0) {
+        ctr[vi].bin_used = min(run, v.bin_cap);
+        sbase = srun ? atomicAdd(&q->total[cls], srun) : 0u;
+    }
+    __syncthreads();
+    const uint32_t qb = sbase;
+    uint2 *items = cls == 0 ? items8 : cls == 1 ? items16 : items32;
+    for (uint32_t i = threadIdx.x; i < n; i += kScanBlock) {
+        const uint32_t c = tile_count[v.tile_base + i];
+        const uint32_t ns = tile_segments(c, tile_off[v.tile_base + i], v.ts_log2);
+        const uint32_t first = qb + tile_item[v.tile_base + i];
+        tile_item[v.tile_base + i] = first;
+        for (uint32_t sgm = 0; sgm < ns; ++sgm) items[first + sgm] = make_uint2(vi, i | (sgm << 18));
+    }
 }
 
 // ------------------------------------------------------------ k_raster
 // LDS record of one (sub-triangle, tile) pair: edge functions relative to
 // the tile's first pixel centre, E_k(P, Q) = C_k + dx_k Q - dy_k P with
-// (P, Q) the pixel offset from that centre in 1/256 px.
-struct alignas(16) LRec {
-    uint32_t flags;   // bits 0..15 sub-tiles touched, 16..18 edge k not owned, 19 slow
-    int c0, c1, c2;   // fast: C_k - notowned_k; slow: low words of C_k
+// (P, Q) the pixel offset from that centre in 1/256 px.  Stored as
+// structure-of-arrays so that a wave can read 64 flags in one conflict-free
+// load, and the coverage fields of one record in three broadcast loads.
+struct alignas(16) LCov {
+    int c0, c1, c2;    // fast: C_k - notowned_k; slow: low words of C_k
     int dx0, dx1, dx2;
     int ny0, ny1, ny2; // -dy_k
-    uint32_t key;
-    float invA;
-    float rw0, rw1, rw2;
-    uint32_t pad;
+    int hi0, hi1, hi2; // slow: high words of C_k
 };
-static_assert(sizeof(LRec) == 64, "LRec");
+struct alignas(16) LRho {
+    float rw0, rw1, rw2, invA;
+};
+static_assert(sizeof(LCov) == 48 && sizeof(LRho) == 16, "LDS records");
 
+// flags: bits 0..15 sub-tiles touched, 16..18 edge k not owned, 19 slow
 constexpr uint32_t kSlow = 1u << 19;
 
-__device__ __forceinline__ long long join64(int hi, int lo)
-{
-    return (long long)(((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo);
-}
-
 template <int TS>
-__device__ __forceinline__ void build_rec(const DView &v, uint32_t key, int ti0, int tj0, LRec &r,
-                                          int hi3[3], bool &rerr)
+__device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int ti0, int tj0,
+                                              LCov &r, LRho &q, bool &rerr)
 {
-    r.flags = 0;
     const uint32_t t = key >> 1;
     const int sub = (int)(key & 1u);
     float P[9];
@@ -396,11 +532,11 @@ __device__ __forceinline__ void build_rec(const DView &v, uint32_t key, int ti0,
     cam_xform(v, P[6], P[7], P[8], c2);
     SVtx<0> a, b, c;
     long long A;
-    if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) return;
+    if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) return 0;
     const PixBox pb = pix_box(v, a, b, c);
     const int bi0 = max(pb.i0 - ti0, 0), bi1 = min(pb.i1 - ti0, TS - 1);
     const int bj0 = max(pb.j0 - tj0, 0), bj1 = min(pb.j1 - tj0, TS - 1);
-    if (bi0 > bi1 || bj0 > bj1) return;
+    if (bi0 > bi1 || bj0 > bj1) return 0;
     constexpr int NS = TS / 8;
     uint32_t mask = 0;
     const int sx0 = bi0 >> 3, sx1 = bi1 >> 3, sy0 = bj0 >> 3, sy1 = bj1 >> 3;
@@ -442,21 +578,25 @@ __device__ __forceinline__ void build_rec(const DView &v, uint32_t key, int ti0,
         r.c1 = (int)(uint32_t)(unsigned long long)C[1];
         r.c2 = (int)(uint32_t)(unsigned long long)C[2];
     }
-    hi3[0] = (int)(C[0] >> 32);
-    hi3[1] = (int)(C[1] >> 32);
-    hi3[2] = (int)(C[2] >> 32);
+    r.hi0 = (int)(C[0] >> 32);
+    r.hi1 = (int)(C[1] >> 32);
+    r.hi2 = (int)(C[2] >> 32);
     r.dx0 = dx[0];
     r.dx1 = dx[1];
     r.dx2 = dx[2];
     r.ny0 = -dy[0];
     r.ny1 = -dy[1];
     r.ny2 = -dy[2];
-    r.key = key;
-    r.invA = 1.0f / (float)A;
-    r.rw0 = a.rw;
-    r.rw1 = b.rw;
-    r.rw2 = c.rw;
-    r.flags = mask | (notown << 16) | (fast ? 0u : kSlow);
+    q.invA = 1.0f / (float)A;
+    q.rw0 = a.rw;
+    q.rw1 = b.rw;
+    q.rw2 = c.rw;
+    return mask | (notown << 16) | (fast ? 0u : kSlow);
+}
+
+__device__ __forceinline__ long long join64(int hi, int lo)
+{
+    return (long long)(((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo);
 }
 
 // Colour, depth and index of the winning sub-triangle at pixel (i, j):
@@ -514,22 +654,156 @@ __device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int
 
 template <int TS>
 __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ views,
-                                                   const uint32_t *__restrict__ lview,
-                                                   const uint32_t *__restrict__ lpre, uint32_t nl,
+                                                   const uint2 *__restrict__ items,
+                                                   DQueue *__restrict__ q,
                                                    DViewCounters *__restrict__ ctr,
                                                    const uint32_t *__restrict__ skey,
                                                    const uint2 *__restrict__ sbox,
                                                    const uint32_t *__restrict__ tile_count,
                                                    const uint32_t *__restrict__ tile_off,
                                                    const uint32_t *__restrict__ bins,
+                                                   uint2 *__restrict__ partial,
                                                    uint32_t *__restrict__ err)
 {
     constexpr int NT = TS * TS;
     constexpr int NS = TS / 8;
-    __shared__ LRec rec[NT];
-    __shared__ int rhi[3][NT];
+    constexpr uint32_t cls = TS == 8 ? 0u : TS == 16 ? 1u : 2u;
+    constexpr uint32_t S = kSegPerTile * NT;
+    __shared__ LCov scov[NT];
+    __shared__ LRho srho[NT];
+    __shared__ uint32_t sflag[NT];
+    __shared__ uint32_t skeyl[NT];
+    __shared__ uint32_t s_item;
 
-    // block -> (view, tile)
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int sx = (int)(wave % NS), sy = (int)(wave / NS);
+    const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
+    const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
+    const uint32_t total = q->total[cls];
+    bool rerr = false;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&q->head[cls], 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const uint2 it = items[item];
+        const uint32_t vi = it.x;
+        const uint32_t tile = it.y & 0x3FFFFu, sgm = it.y >> 18;
+        const DView &v = views[vi];
+        const int tx = (int)(tile % v.tiles_x), ty = (int)(tile / v.tiles_x);
+        const int ti0 = tx * TS, tj0 = ty * TS;
+        const bool inview = ti0 + sx * 8 + li < (int)v.W && tj0 + sy * 8 + lj < (int)v.H;
+        const unsigned long long inmask = __ballot(inview);
+
+        const uint32_t tglob = v.tile_base + tile;
+        const uint32_t cnt = tile_count[tglob];
+        const uint32_t off = tile_off[tglob];
+        const bool over = off == kOverflow;
+        const uint32_t begin = over ? 0u : sgm * S;
+        const uint32_t end = over ? ctr[vi].surv_count : min(begin + S, cnt);
+        const uint32_t *list = bins + v.bin_base + (over ? 0u : off);
+
+        float best_rho = 0.0f;
+        uint32_t best_key = kNone;
+        uint32_t ncov = 0;
+
+        for (uint32_t base = begin; base < end; base += NT) {
+            // stage: each thread rebuilds one list entry's edge setup for this tile
+            {
+                const uint32_t e = base + tid;
+                uint32_t fl = 0, key = 0;
+                LCov r;
+                LRho rq;
+                if (e < end) {
+                    bool go = true;
+                    if (over) {
+                        const uint2 bb = sbox[v.surv_base + e];
+                        const int i0 = (int)(bb.x & 0xFFFFu), j0 = (int)(bb.x >> 16);
+                        const int i1 = (int)(bb.y & 0xFFFFu), j1 = (int)(bb.y >> 16);
+                        go = i1 >= ti0 && i0 < ti0 + TS && j1 >= tj0 && j0 < tj0 + TS;
+                        key = skey[v.surv_base + e];
+                    } else {
+                        key = list[e];
+                    }
+                    if (go) fl = build_rec<TS>(v, key, ti0, tj0, r, rq, rerr);
+                }
+                sflag[tid] = fl;
+                if (fl) {
+                    scov[tid] = r;
+                    srho[tid] = rq;
+                    skeyl[tid] = key;
+                }
+            }
+            __syncthreads();
+            const uint32_t m = min((uint32_t)NT, end - base);
+            for (uint32_t g = 0; g < m; g += 64) {
+                // which of the next 64 records touch this wave's 8x8 sub-tile
+                const uint32_t f = (g + lane < m) ? sflag[g + lane] : 0u;
+                unsigned long long rel = __ballot((f >> wave) & 1u);
+                while (rel) {
+                    const int j = __ffsll((long long)rel) - 1;
+                    rel &= rel - 1ull;
+                    const uint32_t k = g + (uint32_t)j;
+                    const uint32_t fl = __shfl(f, j);
+                    const uint32_t nt = (fl >> 16) & 7u;
+                    const LCov &R = scov[k];
+                    bool cov;
+                    float w0, w1, w2;
+                    if (!(fl & kSlow)) {
+                        const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.dx0, Q) + (uint32_t)__mul24(R.ny0, P));
+                        const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.dx1, Q) + (uint32_t)__mul24(R.ny1, P));
+                        const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.dx2, Q) + (uint32_t)__mul24(R.ny2, P));
+                        cov = (F0 | F1 | F2) >= 0;
+                        if (!__ballot(cov)) continue;
+                        const LRho &Rq = srho[k];
+                        w0 = (float)(F0 + (int)(nt & 1u)) * Rq.rw0;
+                        w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * Rq.rw1;
+                        w2 = (float)(F2 + (int)(nt >> 2)) * Rq.rw2;
+                    } else {
+                        const long long E0 = join64(R.hi0, R.c0) + (long long)R.dx0 * Q + (long long)R.ny0 * P;
+                        const long long E1 = join64(R.hi1, R.c1) + (long long)R.dx1 * Q + (long long)R.ny1 * P;
+                        const long long E2 = join64(R.hi2, R.c2) + (long long)R.dx2 * Q + (long long)R.ny2 * P;
+                        cov = E0 >= (long long)(nt & 1u) && E1 >= (long long)((nt >> 1) & 1u) &&
+                              E2 >= (long long)(nt >> 2);
+                        if (!__ballot(cov)) continue;
+                        const LRho &Rq = srho[k];
+                        w0 = (float)E0 * Rq.rw0;
+                        w1 = (float)E1 * Rq.rw1;
+                        w2 = (float)E2 * Rq.rw2;
+                    }
+                    const float num = (w0 + w1) + w2;
+                    const float rho = num * srho[k].invA;
+                    const uint32_t key = skeyl[k];
+                    ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
+                    const bool better = cov && (rho > best_rho || (rho == best_rho && key < best_key));
+                    best_rho = better ? rho : best_rho;
+                    best_key = better ? key : best_key;
+                }
+            }
+            __syncthreads();
+        }
+        partial[(size_t)item * NT + tid] = make_uint2(__float_as_uint(best_rho), best_key);
+        if (lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
+    }
+    if (rerr) atomicOr(err, kErrRange);
+}
+
+// Per tile: merge the segments' winners (largest 1/w, smaller key on a
+// tie: the same order-free rule), then shade and write the outputs.
+template <int TS>
+__global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ views,
+                                                    const uint32_t *__restrict__ lview,
+                                                    const uint32_t *__restrict__ lpre, uint32_t nl,
+                                                    const uint32_t *__restrict__ tile_count,
+                                                    const uint32_t *__restrict__ tile_off,
+                                                    const uint32_t *__restrict__ tile_item,
+                                                    const uint2 *__restrict__ partial,
+                                                    uint32_t *__restrict__ err)
+{
+    constexpr int NT = TS * TS;
+    constexpr int NS = TS / 8;
     uint32_t lo = 0, hi = nl - 1;
     const uint32_t blk = blockIdx.x;
     while (lo < hi) {
@@ -541,98 +815,23 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
     const DView &v = views[vi];
     const uint32_t tile = blk - lpre[lo];
     const int tx = (int)(tile % v.tiles_x), ty = (int)(tile / v.tiles_x);
-    const int ti0 = tx * TS, tj0 = ty * TS;
-
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    const int sx = (int)(wave % NS), sy = (int)(wave / NS);
-    const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
-    const int pi = ti0 + sx * 8 + li, pj = tj0 + sy * 8 + lj;
-    const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
-    const bool inview = pi < (int)v.W && pj < (int)v.H;
-    const unsigned long long inmask = __ballot(inview);
-    const uint32_t mybit = 1u << wave;
-
+    const int pi = tx * TS + (int)(wave % NS) * 8 + (int)(lane & 7u);
+    const int pj = ty * TS + (int)(wave / NS) * 8 + (int)(lane >> 3);
+    if (pi >= (int)v.W || pj >= (int)v.H) return;
     const uint32_t tglob = v.tile_base + tile;
-    const uint32_t cnt = tile_count[tglob];
-    const uint32_t off = tile_off[tglob];
-    const bool over = cnt != 0 && off == kOverflow;
-    const uint32_t n = over ? ctr[vi].surv_count : cnt;
-    const uint32_t *list = bins + v.bin_base + (over ? 0u : off);
-
+    const uint32_t ns = tile_segments(tile_count[tglob], tile_off[tglob], v.ts_log2);
+    const uint32_t first = tile_item[tglob];
     float best_rho = 0.0f;
     uint32_t best_key = kNone;
-    uint32_t ncov = 0;
-    bool rerr = false;
-
-    for (uint32_t base = 0; base < n; base += NT) {
-        const uint32_t e = base + tid;
-        LRec r;
-        r.flags = 0;
-        int h3[3] = {0, 0, 0};
-        if (e < n) {
-            bool go = true;
-            uint32_t key;
-            if (over) {
-                const uint2 bb = sbox[v.surv_base + e];
-                const int i0 = (int)(bb.x & 0xFFFFu), j0 = (int)(bb.x >> 16);
-                const int i1 = (int)(bb.y & 0xFFFFu), j1 = (int)(bb.y >> 16);
-                go = i1 >= ti0 && i0 < ti0 + TS && j1 >= tj0 && j0 < tj0 + TS;
-                key = skey[v.surv_base + e];
-            } else {
-                key = list[e];
-            }
-            if (go) build_rec<TS>(v, key, ti0, tj0, r, h3, rerr);
+    for (uint32_t s = 0; s < ns; ++s) {
+        const uint2 pr = partial[(size_t)(first + s) * NT + tid];
+        const float rho = __uint_as_float(pr.x);
+        if (pr.y != kNone && (rho > best_rho || (rho == best_rho && pr.y < best_key))) {
+            best_rho = rho;
+            best_key = pr.y;
         }
-        rec[tid] = r;
-        rhi[0][tid] = h3[0];
-        rhi[1][tid] = h3[1];
-        rhi[2][tid] = h3[2];
-        __syncthreads();
-        const uint32_t m = min((uint32_t)NT, n - base);
-        for (uint32_t k = 0; k < m; ++k) {
-            const uint32_t fl = __builtin_amdgcn_readfirstlane(rec[k].flags);
-            if (!(fl & mybit)) continue;
-            const LRec &R = rec[k];
-            const uint32_t nt = (fl >> 16) & 7u;
-            bool cov;
-            float w0, w1, w2;
-            if (!(fl & kSlow)) {
-                const int F0 = R.c0 + __mul24(R.dx0, Q) + __mul24(R.ny0, P);
-                const int F1 = R.c1 + __mul24(R.dx1, Q) + __mul24(R.ny1, P);
-                const int F2 = R.c2 + __mul24(R.dx2, Q) + __mul24(R.ny2, P);
-                cov = (F0 | F1 | F2) >= 0;
-                if (!__ballot(cov)) continue;
-                w0 = (float)(F0 + (int)(nt & 1u)) * R.rw0;
-                w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * R.rw1;
-                w2 = (float)(F2 + (int)(nt >> 2)) * R.rw2;
-            } else {
-                const long long C0 = join64(rhi[0][k], R.c0);
-                const long long C1 = join64(rhi[1][k], R.c1);
-                const long long C2 = join64(rhi[2][k], R.c2);
-                const long long E0 = C0 + (long long)R.dx0 * Q + (long long)R.ny0 * P;
-                const long long E1 = C1 + (long long)R.dx1 * Q + (long long)R.ny1 * P;
-                const long long E2 = C2 + (long long)R.dx2 * Q + (long long)R.ny2 * P;
-                cov = E0 >= (long long)(nt & 1u) && E1 >= (long long)((nt >> 1) & 1u) &&
-                      E2 >= (long long)(nt >> 2);
-                if (!__ballot(cov)) continue;
-                w0 = (float)E0 * R.rw0;
-                w1 = (float)E1 * R.rw1;
-                w2 = (float)E2 * R.rw2;
-            }
-            const float num = (w0 + w1) + w2;
-            const float rho = num * R.invA;
-            const uint32_t key = R.key;
-            ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
-            const bool better = cov && (rho > best_rho || (rho == best_rho && key < best_key));
-            best_rho = better ? rho : best_rho;
-            best_key = better ? key : best_key;
-        }
-        __syncthreads();
     }
-    if (lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
-    if (rerr) atomicOr(err, kErrRange);
-
-    if (!inview) return;
     uint32_t rgb[3] = {0, 0, 0};
     float depth = 0.0f;
     if (best_key != kNone && !resolve(v, best_key, pi, pj, rgb, depth)) atomicOr(err, kErrResolve);
@@ -649,43 +848,89 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
 // ------------------------------------------------------------ host side
 static inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
+static inline void mark(const LaunchPlan &L, int ev, hipStream_t s)
+{
+    if (L.prof) (void)hipEventRecord(L.prof[ev], s);
+}
+
+template <int TS>
+static void launch_raster(const LaunchPlan &L, const RasterLaunch &R, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_raster<TS>, dim3(R.grid), dim3(TS * TS), 0, s, L.views, R.items, L.queue,
+                       L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins, R.partial, L.err);
+}
+
+template <int TS>
+static void launch_resolve(const LaunchPlan &L, const RasterLaunch &R, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resolve<TS>, dim3(R.blocks), dim3(TS * TS), 0, s, L.views, R.lview, R.lpre,
+                       R.nl, L.tile_count, L.tile_off, L.tile_item, R.partial, L.err);
+}
+
+int raster_blocks_per_cu(int ts)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (ts) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<8>, 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<16>, 256, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<32>, 1024, 0); break;
+    default: break;
+    }
+    if (e != hipSuccess) (void)hipGetLastError();
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_render(const LaunchPlan &L, hipStream_t s)
 {
     const uint32_t nreset = L.nviews > L.ntiles ? L.nviews : L.ntiles;
-    if (nreset)
-        hipLaunchKernelGGL(k_reset, dim3(cdiv(nreset, 256)), dim3(256), 0, s, L.ctr, L.nviews,
-                           L.tile_count, L.tile_cursor, L.ntiles);
+    mark(L, 0, s);
+    hipLaunchKernelGGL(k_reset, dim3(cdiv(nreset > 4 ? nreset : 4, 256)), dim3(256), 0, s, L.ctr,
+                       L.nviews, L.tile_count, L.tile_cursor, L.ntiles, L.queue);
+    mark(L, 1, s);
+    mark(L, 2, s);
     if (L.setup_blocks)
         hipLaunchKernelGGL(k_setup, dim3(L.setup_blocks), dim3(kSetupBlock), 0, s, L.views, L.groups,
                            (int)L.ngroups, L.ctr, L.skey, L.sbox, L.err);
+    mark(L, 3, s);
+    mark(L, 4, s);
     hipLaunchKernelGGL(k_bin<false>, dim3(L.bin_grid), dim3(kBinBlock), 0, s, L.views, L.nviews,
                        L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.tile_cursor, L.bins);
+    mark(L, 5, s);
+    mark(L, 6, s);
     hipLaunchKernelGGL(k_bin_scan, dim3(L.nviews), dim3(kScanBlock), 0, s, L.views, L.ctr,
-                       L.tile_count, L.tile_off);
+                       L.tile_count, L.tile_off, L.tile_item, L.queue, L.items[0], L.items[1],
+                       L.items[2]);
+    mark(L, 7, s);
+    mark(L, 8, s);
     hipLaunchKernelGGL(k_bin<true>, dim3(L.bin_grid), dim3(kBinBlock), 0, s, L.views, L.nviews,
                        L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.tile_cursor, L.bins);
+    mark(L, 9, s);
+    for (int k = 0; k < L.nraster; ++k) {
+        const RasterLaunch &R = L.raster[k];
+        if (!R.blocks) continue;
+        const int ph = R.ts == 8 ? 5 : R.ts == 16 ? 6 : 7;
+        mark(L, 2 * ph, s);
+        switch (R.ts) {
+        case 8: launch_raster<8>(L, R, s); break;
+        case 16: launch_raster<16>(L, R, s); break;
+        case 32: launch_raster<32>(L, R, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        mark(L, 2 * ph + 1, s);
+    }
+    mark(L, 2 * kPhaseResolve, s);
     for (int k = 0; k < L.nraster; ++k) {
         const RasterLaunch &R = L.raster[k];
         if (!R.blocks) continue;
         switch (R.ts) {
-        case 8:
-            hipLaunchKernelGGL(k_raster<8>, dim3(R.blocks), dim3(64), 0, s, L.views, R.lview, R.lpre,
-                               R.nl, L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins, L.err);
-            break;
-        case 16:
-            hipLaunchKernelGGL(k_raster<16>, dim3(R.blocks), dim3(256), 0, s, L.views, R.lview,
-                               R.lpre, R.nl, L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins,
-                               L.err);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_raster<32>, dim3(R.blocks), dim3(1024), 0, s, L.views, R.lview,
-                               R.lpre, R.nl, L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins,
-                               L.err);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 8: launch_resolve<8>(L, R, s); break;
+        case 16: launch_resolve<16>(L, R, s); break;
+        case 32: launch_resolve<32>(L, R, s); break;
+        default: return hipErrorInvalidValue;
         }
     }
+    mark(L, 2 * kPhaseResolve + 1, s);
     return hipGetLastError();
 }
 

@@ -233,9 +233,19 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         bin_total += bc;
         d.tile_cap = o.tile_cap ? o.tile_cap : 0xFFFFFFFFu;
         const int c = ts == 8 ? 0 : ts == 16 ? 1 : 2;
-        uint32_t pre = lview[c].empty() ? 0u : lpre[c].back() + dv[lview[c].back()].tiles_x * dv[lview[c].back()].tiles_y;
         lview[c].push_back(k);
-        lpre[c].push_back(pre);
+    }
+    // Raster blocks are dispatched roughly in block order: put the views of
+    // the largest scenes (the longest tile lists) first so that their tiles
+    // do not form the tail of the launch.
+    for (int c = 0; c < 3; ++c) {
+        std::stable_sort(lview[c].begin(), lview[c].end(),
+                         [&](uint32_t a, uint32_t b) { return dv[a].T > dv[b].T; });
+        uint32_t pre = 0;
+        for (uint32_t k : lview[c]) {
+            lpre[c].push_back(pre);
+            pre += dv[k].tiles_x * dv[k].tiles_y;
+        }
     }
     if (tile_total >= kIndexLimit || surv_total >= kIndexLimit || bin_total >= kIndexLimit)
         return HAB_ERR_CAPACITY;
@@ -291,6 +301,22 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     off = align256(off + 8 * surv_total);
     plan.off_bins = off;
     off = align256(off + 4 * bin_total);
+    plan.off_titem = off;
+    off = align256(off + 4 * tile_total);
+    plan.off_queue = off;
+    off = align256(off + sizeof(DQueue));
+    // raster work items: a tile holds at most one item per kSegPerTile*TS^2
+    // list entries (plus one), so a view needs at most tiles + bin_cap / S
+    uint64_t item_cap[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+        const uint64_t S = (uint64_t)kSegPerTile << (6 + 2 * c);
+        for (uint32_t k : lview[c])
+            item_cap[c] += (uint64_t)dv[k].tiles_x * dv[k].tiles_y + (dv[k].bin_cap + S - 1) / S;
+        plan.off_items[c] = off;
+        off = align256(off + 8 * item_cap[c]);
+        plan.off_partial[c] = off;
+        off = align256(off + 8 * item_cap[c] * (64ull << (2 * c)));
+    }
     plan.arena_bytes = off;
 
     LaunchPlan &L = plan.L;
@@ -303,6 +329,10 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     for (uint32_t k = 0; k < n; ++k) ub += cdiv(dv[k].surv_cap, kBinBlock * kBinItems);
     L.bin_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ub, 8ull * (ctx ? ctx->cu_count : 256)));
     L.nraster = 0;
+    const uint32_t cus = ctx ? (uint32_t)ctx->cu_count : 256u;
+    const uint32_t kBlocksPerCu[3] = {ctx ? (uint32_t)ctx->raster_bpc[0] : 1u,
+                                      ctx ? (uint32_t)ctx->raster_bpc[1] : 1u,
+                                      ctx ? (uint32_t)ctx->raster_bpc[2] : 1u};
     for (int c = 0; c < 3; ++c) {
         if (lview[c].empty()) continue;
         RasterLaunch &R = L.raster[L.nraster++];
@@ -310,8 +340,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         R.nl = (uint32_t)lview[c].size();
         const DView &last = dv[lview[c].back()];
         R.blocks = lpre[c].back() + last.tiles_x * last.tiles_y;
-        R.lview = reinterpret_cast<const uint32_t *>(plan.off_lview[c]);   // bound later
-        R.lpre = reinterpret_cast<const uint32_t *>(plan.off_lpre[c]);
+        R.item_cap = item_cap[c];
+        R.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(item_cap[c], (uint64_t)cus * kBlocksPerCu[c]));
     }
     return HAB_OK;
 }
@@ -329,12 +359,17 @@ void bind_plan(Plan &plan, void *arena, uint32_t *err)
     L.skey = reinterpret_cast<uint32_t *>(b + plan.off_skey);
     L.sbox = reinterpret_cast<uint2 *>(b + plan.off_sbox);
     L.bins = reinterpret_cast<uint32_t *>(b + plan.off_bins);
+    L.tile_item = reinterpret_cast<uint32_t *>(b + plan.off_titem);
+    L.queue = reinterpret_cast<DQueue *>(b + plan.off_queue);
     L.err = err;
+    for (int c = 0; c < 3; ++c) L.items[c] = reinterpret_cast<uint2 *>(b + plan.off_items[c]);
     for (int k = 0; k < L.nraster; ++k) {
         RasterLaunch &R = L.raster[k];
         const int c = R.ts == 8 ? 0 : R.ts == 16 ? 1 : 2;
         R.lview = reinterpret_cast<const uint32_t *>(b + plan.off_lview[c]);
         R.lpre = reinterpret_cast<const uint32_t *>(b + plan.off_lpre[c]);
+        R.items = reinterpret_cast<uint2 *>(b + plan.off_items[c]);
+        R.partial = reinterpret_cast<uint2 *>(b + plan.off_partial[c]);
     }
 }
 
@@ -348,7 +383,10 @@ Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context
         uint64_t nt = (uint64_t)cdiv(v[k].sensor.width, ts) * cdiv(v[k].sensor.height, ts);
         tiles += nt;
         uint64_t bc = std::max<uint64_t>((uint64_t)std::ceil((double)bf * v[k].scene->T), 1024);
-        bytes += 2ull * v[k].scene->T * 12ull + bc * 4ull + nt * 12ull + sizeof(DView) + 64;
+        const uint64_t S = (uint64_t)kSegPerTile * ts * ts;
+        const uint64_t items = nt + (bc + S - 1) / S;
+        bytes += 2ull * v[k].scene->T * 12ull + bc * 4ull + nt * 16ull + sizeof(DView) + 64 +
+                 items * 8ull * (1 + (uint64_t)ts * ts);
     }
     f.desc_bytes = n * (sizeof(DView) + 32) + 4096;
     f.arena_bytes = bytes + f.desc_bytes + 16 * 256;
@@ -375,6 +413,20 @@ hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint3
     HAB_HIP(hipEventRecord(ws.slots[slot].ev, s));
     ws.slots[slot].pending = true;
     bind_plan(plan, ws.arena, ctx->err);
+    hab_context::ProfSet *ps = nullptr;
+    if (ctx->prof_on) {
+        if (ctx->prof_used == ctx->prof_sets.size()) {
+            hab_context::ProfSet fresh{};
+            for (int e = 0; e < kProfEvents; ++e) HAB_HIP(hipEventCreate(&fresh.ev[e]));
+            ctx->prof_sets.push_back(fresh);
+        }
+        ps = &ctx->prof_sets[ctx->prof_used++];
+        ps->mask = 0x1Fu | (1u << kPhaseResolve);
+        for (int k = 0; k < plan.L.nraster; ++k)
+            if (plan.L.raster[k].blocks)
+                ps->mask |= 1u << (plan.L.raster[k].ts == 8 ? 5 : plan.L.raster[k].ts == 16 ? 6 : 7);
+        plan.L.prof = ps->ev;
+    }
     HAB_HIP(launch_render(plan.L, s));
     HAB_HIP(hipEventRecord(ws.done, s));
     ws.has_done = true;

@@ -90,6 +90,7 @@ struct Plan {
     size_t off_views = 0, off_groups = 0, off_lview[3] = {0, 0, 0}, off_lpre[3] = {0, 0, 0};
     size_t off_ctr = 0, off_tcount = 0, off_toff = 0, off_tcur = 0;
     size_t off_skey = 0, off_sbox = 0, off_bins = 0;
+    size_t off_titem = 0, off_queue = 0, off_items[3] = {0, 0, 0}, off_partial[3] = {0, 0, 0};
     std::vector<uint32_t> order;     // sorted position -> caller index
     uint32_t n = 0;
 };
@@ -110,6 +111,15 @@ struct hab_context {
     std::vector<habmi::Tuned> tuned;  // autotune table
     std::mutex tune_mu;
     int cu_count = 256;
+    int raster_bpc[3] = {1, 1, 1};    // resident raster blocks per CU, tile 8/16/32
+    // per-phase event timing (hab_profile_enable)
+    struct ProfSet {
+        hipEvent_t ev[habmi::kProfEvents];
+        uint32_t mask;            // phases recorded in this set
+    };
+    bool prof_on = false;
+    std::vector<ProfSet> prof_sets;
+    size_t prof_used = 0;
 };
 
 struct hab_scene : habmi::Scene {};

@@ -212,6 +212,17 @@ class Context:
     def get_error(self) -> int:
         return int(self.lib.hab_get_error(self.h))
 
+    # ------------------------------------------------------------ profiling
+    def profile(self, on: bool = True):
+        B.check(self.lib.hab_profile_enable(self.h, 1 if on else 0), "hab_profile_enable")
+
+    def profile_read(self):
+        """Per-phase summed device ms and launch counts since the last read."""
+        t = B.PhaseTimes()
+        B.check(self.lib.hab_profile_read(self.h, C.byref(t)), "hab_profile_read")
+        return {name: {"ms": t.ms[k], "launches": int(t.launches[k])}
+                for k, name in enumerate(B.PHASES) if t.launches[k]}
+
     # ------------------------------------------------------------ stepper
     def stepper(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None):
         return Stepper(self, items, tile_size, bin_factor, tile_cap, stream)
