@@ -258,3 +258,70 @@ class Stepper:
         if self.h:
             B.check(self.ctx.lib.hab_stepper_destroy(self.h), "hab_stepper_destroy")
             self.h = None
+
+
+class Server:
+    """Continuous-batching request loop over the context's resident scenes.
+
+    submit() is non-blocking and returns a ticket; the request's output
+    tensors must stay alive until poll()/wait() reports it complete.  While
+    a server runs, the context is used only through it."""
+
+    def __init__(self, ctx: Context, num_streams=2, max_batch=256, memory_budget=8 << 30,
+                 max_queue=65536, max_wait_us=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        cfg = B.ServerCfg(int(num_streams), int(max_batch), int(memory_budget), int(max_queue),
+                          int(max_wait_us))
+        h = C.c_void_p()
+        B.check(self.lib.hab_server_create(ctx.h, C.byref(cfg), C.byref(h)), "hab_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, scene, sensor, pose, rgb=None, depth=None, tri=None) -> int:
+        check_output("rgb", rgb, 1, sensor)
+        check_output("depth", depth, 1, sensor)
+        check_output("tri", tri, 1, sensor)
+        v = B.View()
+        v.scene = scene.ptr
+        v.sensor = C.pointer(sensor)
+        v.pose = B.pose_to_c(pose)
+        v.out_rgb = None if rgb is None else int(rgb.data_ptr())
+        v.out_depth = None if depth is None else int(depth.data_ptr())
+        v.out_tri = None if tri is None else int(tri.data_ptr())
+        t = C.c_uint64()
+        B.check(self.lib.hab_server_submit(self.h, C.byref(v), C.byref(t)), "hab_server_submit")
+        self._keep[t.value] = (rgb, depth, tri)
+        return t.value
+
+    @staticmethod
+    def _stats(rs):
+        return {"submit_ns": rs.submit_ns, "launch_ns": rs.launch_ns, "done_ns": rs.done_ns,
+                "batch_size": rs.batch_size, "batch_id": rs.batch_id}
+
+    def poll(self, ticket: int):
+        rs = B.RequestStats()
+        s = self.lib.hab_server_poll(self.h, C.c_uint64(ticket), C.byref(rs))
+        if s == B.HAB_ERR_NOT_READY:
+            return None
+        self._keep.pop(ticket, None)
+        B.check(s, "hab_server_poll")
+        return self._stats(rs)
+
+    def wait(self, ticket: int):
+        rs = B.RequestStats()
+        s = self.lib.hab_server_wait(self.h, C.c_uint64(ticket), C.byref(rs))
+        self._keep.pop(ticket, None)
+        B.check(s, "hab_server_wait")
+        return self._stats(rs)
+
+    def stats(self):
+        st = B.ServerStats()
+        B.check(self.lib.hab_server_stats_get(self.h, C.byref(st)), "hab_server_stats_get")
+        return {k: getattr(st, k) for k, _ in B.ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            B.check(self.lib.hab_server_destroy(self.h), "hab_server_destroy")
+            self.h = None
+            self._keep.clear()
