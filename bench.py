@@ -46,12 +46,33 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--per-view-steps", type=int, default=10)
     ap.add_argument("--latency-steps", type=int, default=100)
-    ap.add_argument("--cpu-views", type=int, default=512)
+    ap.add_argument("--cpu-views", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the batched path (warmup + steps), for profiler runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run plain 256 MiB device copies (reference for FETCH/WRITE_SIZE)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving curve: resident scenes, Poisson arrivals, p50/p99 vs throughput")
+    ap.add_argument("--serve-agents", type=int, default=512)
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-total-tri", type=int, default=20_000_000)
+    ap.add_argument("--serve-scenes", type=int, default=32)
     a = ap.parse_args()
+    if a.serve:
+        return serve(a)
+    if a.copy_calibration:
+        import torch
+        n = 256 << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": True, "bytes_per_copy": n, "copies": 4}), flush=True)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build renders on one GPU; --gpus must be 1 "
                           "(the multi-GPU sharding is a design note only)"}))
@@ -246,6 +267,54 @@ def main():
     }
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+def serve(a):
+    """Serving curve on the serve_32scenes workload (32 resident jittered
+    apartments, sum T ~ 20M, agents with mixed 128/256/512 resolutions and
+    D/RGB/RGB+D sensors)."""
+    import torch
+    import paper_1904_01201_amd as P
+    from paper_1904_01201_amd import loadgen
+    from scenegen import configs
+
+    t0 = time.time()
+    w = configs.serve_32scenes(num_agents=a.serve_agents, steps=64, total_T=a.serve_total_tri,
+                               num_scenes=a.serve_scenes)
+    log(f"serve workload: {len(w.scenes)} scenes, sum T = {sum(s.num_triangles for s in w.scenes)}, "
+        f"{w.num_envs} agents, generated in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    ctx = P.Context(0)
+    hs = [ctx.upload_scene(s) for s in w.scenes]
+    resident = sum(h.device_bytes for h in hs)
+    sensors = [ctx.sensor(s.width, s.height, s.hfov_deg, s.near_m, s.outputs) for s in w.env_sensor]
+    agents = loadgen.Agents(ctx, hs, w.env_scene, sensors, w.poses)
+    srv = P.Server(ctx, num_streams=3, max_batch=256)
+    sat, lat_sat = loadgen.saturate(srv, agents, seconds=a.serve_seconds)
+    log(f"closed-loop saturation: {sat:.0f} requests/s, p50 {np.percentile(lat_sat, 50):.2f} ms")
+    curve = []
+    for frac in (0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.2):
+        thr, lat, bs = loadgen.open_loop(srv, agents, rate=frac * sat, seconds=a.serve_seconds,
+                                         seed=int(frac * 100))
+        pt = {"offered_frac": frac, "offered_rps": round(frac * sat, 1), "throughput_rps": round(thr, 1),
+              "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
+              "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
+              "mean_batch": round(float(bs.mean()), 1) if bs.size else None, "requests": int(lat.size)}
+        curve.append(pt)
+        log(f"offered {frac:.1f}x: {pt}")
+    st = srv.stats()
+    srv.close()
+    assert ctx.get_error() == 0
+    ctx.close()
+    px = [s.width * s.height for s in w.env_sensor]
+    print(json.dumps({"metric": "serving: step-request latency p50/p99 vs throughput",
+                      "unit": "requests/s", "saturation_rps": round(sat, 1),
+                      "config": {"workload": w.name, "scenes": len(w.scenes),
+                                 "total_triangles": int(sum(s.num_triangles for s in w.scenes)),
+                                 "resident_bytes": int(resident), "agents": w.num_envs,
+                                 "mean_pixels_per_request": round(float(np.mean(px)), 1),
+                                 "streams": 3, "max_batch": 256},
+                      "curve": curve, "server_stats": st}), flush=True)
 
 
 if __name__ == "__main__":

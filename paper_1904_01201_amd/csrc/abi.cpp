@@ -99,6 +99,7 @@ hab_status hab_shutdown(hab_context *ctx)
             (void)hipFree(s->pos);
             (void)hipFree(s->col);
             (void)hipFree(s->idx);
+            (void)hipFree(s->cbox);
             delete static_cast<hab_scene *>(s);
         }
         ctx->scenes.clear();
@@ -143,6 +144,24 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
                 lo[a] = std::min(lo[a], x);
                 hi[a] = std::max(hi[a], x);
             }
+        // bounding box of every 64 consecutive triangles (one setup wave):
+        // exact float min/max of the vertex coordinates
+        const uint32_t ncl = (T + kCluster - 1) / kCluster;
+        std::vector<float4> cbox(2 * (size_t)std::max<uint32_t>(ncl, 1));
+        for (uint32_t c = 0; c < ncl; ++c) {
+            float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+            const uint32_t t1 = std::min<uint32_t>(T, (c + 1) * kCluster);
+            for (uint32_t t = c * kCluster; t < t1; ++t)
+                for (int k = 0; k < 3; ++k) {
+                    const float *q = m->positions + 3ull * m->indices[3ull * t + k];
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = std::min(mn[a], q[a]);
+                        mx[a] = std::max(mx[a], q[a]);
+                    }
+                }
+            cbox[2 * c] = make_float4(mn[0], mn[1], mn[2], 0.0f);
+            cbox[2 * c + 1] = make_float4(mx[0], mx[1], mx[2], 0.0f);
+        }
         std::vector<uint32_t> col(V);
         for (uint64_t k = 0; k < V; ++k) {
             if (m->colors)
@@ -162,28 +181,32 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             s->hi[a] = hi[a];
         }
         const size_t bp = 12ull * V, bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
-        bool ok = hipMalloc((void **)&s->pos, bp) == hipSuccess &&
-                  hipMalloc((void **)&s->col, bc) == hipSuccess &&
-                  hipMalloc((void **)&s->idx, bi) == hipSuccess;
-        if (!ok) {
-            (void)hipGetLastError();
+        const size_t bb = sizeof(float4) * cbox.size();
+        auto drop = [&]() {
             (void)hipFree(s->pos);
             (void)hipFree(s->col);
             (void)hipFree(s->idx);
+            (void)hipFree(s->cbox);
             delete s;
+        };
+        bool ok = hipMalloc((void **)&s->pos, bp) == hipSuccess &&
+                  hipMalloc((void **)&s->col, bc) == hipSuccess &&
+                  hipMalloc((void **)&s->idx, bi) == hipSuccess &&
+                  hipMalloc((void **)&s->cbox, bb) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            drop();
             return HAB_ERR_OUT_OF_MEMORY;
         }
-        s->bytes = bp + bc + bi;
+        s->bytes = bp + bc + bi + bb;
         hipError_t e = hipMemcpyAsync(s->pos, m->positions, bp, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s->col, col.data(), bc, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && T)
             e = hipMemcpyAsync(s->idx, m->indices, 12ull * T, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->cbox, cbox.data(), bb, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
-            (void)hipFree(s->pos);
-            (void)hipFree(s->col);
-            (void)hipFree(s->idx);
-            delete s;
+            drop();
             return HAB_ERR_DEVICE;
         }
         ctx->scenes.push_back(s);
@@ -204,6 +227,7 @@ hab_status hab_scene_release(hab_context *ctx, hab_scene *scene)
         (void)hipFree(scene->pos);
         (void)hipFree(scene->col);
         (void)hipFree(scene->idx);
+        (void)hipFree(scene->cbox);
         ctx->scenes.erase(it);
         delete scene;
         return HAB_OK;

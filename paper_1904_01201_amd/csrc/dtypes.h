@@ -1,5 +1,6 @@
 // Plain structures shared by the host runtime and the kernels.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace habmi {
@@ -10,6 +11,7 @@ constexpr int kSetupBlock = 256;              // threads per block in setup
 constexpr int kBinBlock = 256;                // threads per block in count/scatter
 constexpr int kBinItems = 4;                  // survivors per thread in count/scatter
 constexpr int kScanBlock = 1024;
+constexpr int kCluster = 64;                  // triangles per culling cluster (one wave)
 
 // Error bits of the sticky device error word.
 constexpr uint32_t kErrRange = 1u;            // a vertex snapped outside |X|,|Y| < 2^29
@@ -36,30 +38,26 @@ struct alignas(16) DView {
     uint32_t bin_base;          // first entry in the bin array
     uint32_t bin_cap;           // entries available to this view
     uint32_t tile_cap;          // entries one tile may hold (else overflow)
-    uint32_t pad[6];
+    uint32_t pair_base;         // first entry of this view's visible-cluster segment
+    const float4 *cbox;         // per 64-triangle cluster: (min xyz, -) (max xyz, -)
+    uint32_t pad[2];
 };
 static_assert(sizeof(DView) == 192, "DView layout");
-
-// A run of consecutive views that share one scene: setup fetches each
-// triangle once and transforms it for every view of the group.
-struct DGroup {
-    uint32_t first_view;
-    uint32_t num_views;
-    uint32_t T;
-    uint32_t block_start;       // first setup block of this group
-};
 
 // Work queues of the raster stage, one per tile size (8, 16, 32): `total`
 // items were appended by the scan, `head` is the next one to hand out.
 struct DQueue {
     uint32_t head[4];
     uint32_t total[4];
+    uint32_t pad[4];
 };
 
 // Per-view counters (zeroed at the start of every launch sequence).
 struct DViewCounters {
     uint32_t surv_count;        // survivors appended by setup
     uint32_t bin_used;          // entries the scan assigned
+    uint32_t vis_clusters;      // clusters that passed the view's frustum test
+    uint32_t pad;
     unsigned long long bbox_tests;
     unsigned long long covered;
 };

@@ -29,9 +29,8 @@ struct RasterLaunch {
 struct LaunchPlan {
     const DView *views;
     uint32_t nviews;
-    const DGroup *groups;
-    uint32_t ngroups;
-    uint32_t setup_blocks;
+    uint32_t setup_grid;       // setup grid (waves stride over the visible cluster runs)
+    uint32_t *pairs;           // visible clusters, one segment per view
     DViewCounters *ctr;
     uint32_t *skey;
     uint2 *sbox;

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(256) void k_reset(DViewCounters *__restrict__ ctr, 
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i < nviews) {
+        ctr[i].vis_clusters = 0;
         ctr[i].surv_count = 0;
         ctr[i].bin_used = 0;
         ctr[i].bbox_tests = 0;
@@ -187,93 +188,171 @@ __device__ __forceinline__ void survive(const DView &v, const float P[9], bool v
     }
 }
 
+// Conservative frustum test of a 64-triangle cluster's bounding box for
+// view v, in fp64 over the box's eight corners.  The box counts as outside
+// only when all corners lie beyond one side plane of the per-vertex
+// rejection in `survive` by a margin (fS + K) 2^-18 |d|_1 that exceeds that
+// test's fp32 error (< 2^-20 |d|_1 per camera coordinate), or all lie in
+// front of the near plane by 2^-18 |d|_1: then every vertex of every
+// triangle in the box fails in the same way, each triangle (and each
+// near-clipped piece, a convex combination of its vertices) is culled by
+// the exact path, and skipping the cluster changes nothing.
+__device__ __forceinline__ bool box_outside(const DView &v, float4 mn, float4 mx)
+{
+    const double fS = (double)v.fS;
+    const double Kx = (double)((v.cxS + 1024.0f) * 1.0000152587890625f);
+    const double Ky = (double)((v.cyS + 1024.0f) * 1.0000152587890625f);
+    double X[8], Y[8], W[8], l1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const double dx = (double)((c & 1) ? mx.x : mn.x) - (double)v.p[0];
+        const double dy = (double)((c & 2) ? mx.y : mn.y) - (double)v.p[1];
+        const double dz = (double)((c & 4) ? mx.z : mn.z) - (double)v.p[2];
+        X[c] = (double)v.R[0] * dx + (double)v.R[3] * dy + (double)v.R[6] * dz;
+        Y[c] = (double)v.R[1] * dx + (double)v.R[4] * dy + (double)v.R[7] * dz;
+        W[c] = -((double)v.R[2] * dx + (double)v.R[5] * dy + (double)v.R[8] * dz);
+        l1 = fmax(l1, fabs(dx) + fabs(dy) + fabs(dz));
+    }
+    const double mg = (fS + fmax(Kx, Ky)) * 0x1p-18 * l1, mz = 0x1p-18 * l1;
+    bool r = true, l = true, u = true, d = true, n = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        r = r && X[c] * fS - Kx * W[c] > mg;
+        l = l && -X[c] * fS - Kx * W[c] > mg;
+        u = u && Y[c] * fS - Ky * W[c] > mg;
+        d = d && -Y[c] * fS - Ky * W[c] > mg;
+        n = n && W[c] < (double)v.zn - mz;
+    }
+    return r || l || u || d || n;
+}
+
+// One block per view: test every 64-triangle cluster of the view's scene
+// against the view's frustum and write the visible ones, in cluster order,
+// to the view's segment of the pair list (a block scan: no atomics).
+__global__ __launch_bounds__(kScanBlock) void k_cull(const DView *__restrict__ views,
+                                                     DViewCounters *__restrict__ ctr,
+                                                     uint32_t *__restrict__ vis_clusters)
+{
+    __shared__ uint32_t wtot[kScanBlock / 64];
+    const uint32_t vi = blockIdx.x;
+    const DView &v = views[vi];
+    const uint32_t ncl = (v.T + kCluster - 1) / kCluster;
+    uint32_t run = 0;
+    for (uint32_t base = 0; base < ncl; base += kScanBlock) {
+        const uint32_t c = base + threadIdx.x;
+        const bool vis = c < ncl && !(v.cbox && box_outside(v, v.cbox[2 * c], v.cbox[2 * c + 1]));
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<kScanBlock>(vis ? 1u : 0u, wtot, &tot);
+        if (vis) vis_clusters[v.pair_base + run + ex] = c;
+        run += tot;
+    }
+    if (threadIdx.x == 0) ctr[vi].vis_clusters = run;
+}
+
+// Work items of k_setup: (view, run of kRun visible clusters).  Each block
+// builds the prefix of item counts over the views in LDS, then its waves
+// stride over the items.  A wave sets up one triangle of each of the run's
+// clusters per lane (independent loads in flight together), keeps the
+// survivors in registers, reserves their slots with one atomic and writes
+// them with their boxes.
+constexpr uint32_t kRun = 4;
+
 __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__ views,
-                                                       const DGroup *__restrict__ groups,
-                                                       int ngroups, DViewCounters *__restrict__ ctr,
+                                                       uint32_t nviews,
+                                                       DViewCounters *__restrict__ ctr,
+                                                       const uint32_t *__restrict__ vis_clusters,
                                                        uint32_t *__restrict__ skey,
                                                        uint2 *__restrict__ sbox,
                                                        uint32_t *__restrict__ err)
 {
-    int lo = 0, hi = ngroups - 1;
-    const int b = (int)blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((int)groups[mid].block_start <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const DGroup G = groups[lo];
-    const uint32_t t = (uint32_t)(b - (int)G.block_start) * kSetupBlock + threadIdx.x;
-    const bool valid = t < G.T;
-    const DView &vg = views[G.first_view];
-    float P[9];
-    uint32_t vid[3];
-    if (valid) {
-        load_tri(vg, t, P, vid);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) P[k] = 0.0f;
+    __shared__ uint32_t pre[kMaxViews];
+    __shared__ uint32_t wtot[kSetupBlock / 64];
+    uint32_t total;
+    {
+        const uint32_t seg = (nviews + kSetupBlock - 1) / kSetupBlock;
+        const uint32_t i0 = threadIdx.x * seg, i1 = min(i0 + seg, nviews);
+        uint32_t local = 0;
+        for (uint32_t i = i0; i < i1; ++i) local += (ctr[i].vis_clusters + kRun - 1) / kRun;
+        uint32_t run = block_excl_scan<kSetupBlock>(local, wtot, &total);
+        for (uint32_t i = i0; i < i1; ++i) {
+            pre[i] = run;
+            run += (ctr[i].vis_clusters + kRun - 1) / kRun;
+        }
+        __syncthreads();
     }
     const uint32_t lane = lane_id();
     const unsigned long long lt = lanemask_lt();
-    const uint32_t nv = G.num_views;   // <= 16: two survival bits per view fit one word
+    const uint32_t wave0 = (blockIdx.x * kSetupBlock + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * kSetupBlock) >> 6;
     bool rerr = false;
-
-    // pass 1: which sub-triangles survive in which view; lane k collects
-    // the wave's totals for view k
-    uint32_t bits = 0, totv = 0, alov = 0, ahiv = 0;
-    for (uint32_t k = 0; k < nv; ++k) {
-        const DView &v = views[G.first_view + k];
-        bool s0, s1;
-        PixBox b0, b1;
-        survive(v, P, valid, s0, s1, b0, b1, rerr);
-        bits |= (s0 ? 1u : 0u) << (2 * k);
-        bits |= (s1 ? 1u : 0u) << (2 * k + 1);
-        const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
-        if (m0 | m1) {
-            uint32_t area = 0;
-            if (s0) area += (uint32_t)(b0.i1 - b0.i0 + 1) * (uint32_t)(b0.j1 - b0.j0 + 1);
-            if (s1) area += (uint32_t)(b1.i1 - b1.i0 + 1) * (uint32_t)(b1.j1 - b1.j0 + 1);
-            // two boxes of at most 2^24 pixels per lane: the two halves of
-            // the wave sum cannot overflow
-            const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
-            const uint32_t ahi = wave_sum_u32(area >> 16);
-            if (lane == k) {
-                totv = (uint32_t)(__popcll(m0) + __popcll(m1));
-                alov = alo;
-                ahiv = ahi;
+    for (uint32_t item = wave0; item < total; item += nwaves) {
+        uint32_t lo = 0, hi = nviews - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t vi = lo;
+        const DView &v = views[vi];
+        const uint32_t first = (item - pre[vi]) * kRun;
+        const uint32_t nrun = min(kRun, ctr[vi].vis_clusters - first);
+        uint32_t t[kRun];
+        bool valid[kRun];
+        float P[kRun][9];
+#pragma unroll
+        for (uint32_t j = 0; j < kRun; ++j) {
+            t[j] = j < nrun ? vis_clusters[v.pair_base + first + j] * kCluster + lane : 0xFFFFFFFFu;
+            valid[j] = j < nrun && t[j] < v.T;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kRun; ++j) {
+            uint32_t vid[3];
+            if (valid[j]) {
+                load_tri(v, t[j], P[j], vid);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) P[j][k] = 0.0f;
             }
         }
-    }
-    // one atomic round trip for all views of the group (lane k: view k)
-    uint32_t basev = 0;
-    if (lane < nv && totv) {
-        basev = atomicAdd(&ctr[G.first_view + lane].surv_count, totv);
-        atomicAdd(&ctr[G.first_view + lane].bbox_tests,
-                  (unsigned long long)alov + ((unsigned long long)ahiv << 16));
-    }
-    // pass 2: rebuild the surviving boxes and write them at their slots
-    for (uint32_t k = 0; k < nv; ++k) {
-        const uint32_t tot = __shfl(totv, (int)k);
-        if (!tot) continue;
-        const uint32_t base = __shfl(basev, (int)k);
-        const bool s0 = (bits >> (2 * k)) & 1u, s1 = (bits >> (2 * k + 1)) & 1u;
-        const uint32_t pre = (uint32_t)(__popcll(__ballot(s0) & lt) + __popcll(__ballot(s1) & lt));
-        if (s0 || s1) {
-            const DView &v = views[G.first_view + k];
-            bool r0, r1;
-            PixBox b0, b1;
-            survive(v, P, valid, r0, r1, b0, b1, rerr);
-            uint32_t o = v.surv_base + base + pre;
-            if (s0) {
-                skey[o] = 2u * t;
-                sbox[o] = pack_box(b0);
-                ++o;
-            }
-            if (s1) {
-                skey[o] = 2u * t + 1u;
-                sbox[o] = pack_box(b1);
-            }
+        bool s[kRun][2];
+        PixBox bx[kRun][2];
+        uint32_t area = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kRun; ++j) {
+            survive(v, P[j], valid[j], s[j][0], s[j][1], bx[j][0], bx[j][1], rerr);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (s[j][q]) area += (uint32_t)(bx[j][q].i1 - bx[j][q].i0 + 1) * (uint32_t)(bx[j][q].j1 - bx[j][q].j0 + 1);
         }
+        // slots in (cluster, sub, lane) order
+        uint32_t cnt = 0, mine[kRun][2];
+#pragma unroll
+        for (uint32_t j = 0; j < kRun; ++j)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const unsigned long long m = __ballot(s[j][q]);
+                mine[j][q] = cnt + (uint32_t)__popcll(m & lt);
+                cnt += (uint32_t)__popcll(m);
+            }
+        if (!cnt) continue;
+        // eight boxes of at most 2^24 pixels per lane: the two halves of
+        // the wave sum cannot overflow
+        const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
+        const uint32_t ahi = wave_sum_u32(area >> 16);
+        uint32_t base = 0;
+        if (lane == 0) {
+            base = atomicAdd(&ctr[vi].surv_count, cnt);
+            atomicAdd(&ctr[vi].bbox_tests, (unsigned long long)alo + ((unsigned long long)ahi << 16));
+        }
+        base = __shfl(base, 0) + v.surv_base;
+#pragma unroll
+        for (uint32_t j = 0; j < kRun; ++j)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (s[j][q]) {
+                    skey[base + mine[j][q]] = 2u * t[j] + (uint32_t)q;
+                    sbox[base + mine[j][q]] = pack_box(bx[j][q]);
+                }
     }
     if (rerr) atomicOr(err, kErrRange);
 }
@@ -500,26 +579,34 @@ __global__ __launch_bounds__(kScanBlock) void k_bin_scan(const DView *__restrict
 // ------------------------------------------------------------ k_raster
 // LDS record of one (sub-triangle, tile) pair: edge functions relative to
 // the tile's first pixel centre, E_k(P, Q) = C_k + dx_k Q - dy_k P with
-// (P, Q) the pixel offset from that centre in 1/256 px.  Stored as
-// structure-of-arrays so that a wave can read 64 flags in one conflict-free
-// load, and the coverage fields of one record in three broadcast loads.
-struct alignas(16) LCov {
+// (P, Q) the pixel offset from that centre in 1/256 px.  Everything a visit
+// needs for the common (packed) case sits in one 48-byte block, read with
+// three 16-byte loads in one round trip; unpacked and int64 records keep
+// their extra words in a second array.
+struct alignas(16) LRec {
     int c0, c1, c2;    // fast: C_k - notowned_k; slow: low words of C_k
-    int dx0, dx1, dx2;
-    int ny0, ny1, ny2; // -dy_k
-    int hi0, hi1, hi2; // slow: high words of C_k
-};
-struct alignas(16) LRho {
+    int e0, e1, e2;    // packed: (dx_k, -dy_k) as 16-bit pairs; else dx_k
     float rw0, rw1, rw2, invA;
+    uint32_t key;
+    uint32_t flags;
 };
-static_assert(sizeof(LCov) == 48 && sizeof(LRho) == 16, "LDS records");
+struct alignas(16) LExt {
+    int ny0, ny1, ny2; // -dy_k (unpacked records)
+    int hi0, hi1, hi2; // slow: high words of C_k
+    int pad0, pad1;
+};
+static_assert(sizeof(LRec) == 48 && sizeof(LExt) == 32, "LDS records");
 
 // flags: bits 0..15 sub-tiles touched, 16..18 edge k not owned, 19 slow
+// (int64 edge values), 20 packed (every edge delta fits int16)
 constexpr uint32_t kSlow = 1u << 19;
+constexpr uint32_t kPacked = 1u << 20;
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
 
 template <int TS>
 __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int ti0, int tj0,
-                                              LCov &r, LRho &q, bool &rerr)
+                                              LRec &r, LExt &x, bool &rerr)
 {
     const uint32_t t = key >> 1;
     const int sub = (int)(key & 1u);
@@ -569,6 +656,9 @@ __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int 
         fast = fast && emax <= (1ll << 29) && emin >= -(1ll << 29) &&
                dx[k] < (1 << 22) && dx[k] > -(1 << 22) && dy[k] < (1 << 22) && dy[k] > -(1 << 22);
     }
+    bool packed = fast;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) packed = packed && dx[k] < 32768 && dx[k] > -32768 && dy[k] < 32768 && dy[k] > -32768;
     if (fast) {
         r.c0 = (int)(C[0] - (long long)(notown & 1u));
         r.c1 = (int)(C[1] - (long long)((notown >> 1) & 1u));
@@ -578,20 +668,28 @@ __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int 
         r.c1 = (int)(uint32_t)(unsigned long long)C[1];
         r.c2 = (int)(uint32_t)(unsigned long long)C[2];
     }
-    r.hi0 = (int)(C[0] >> 32);
-    r.hi1 = (int)(C[1] >> 32);
-    r.hi2 = (int)(C[2] >> 32);
-    r.dx0 = dx[0];
-    r.dx1 = dx[1];
-    r.dx2 = dx[2];
-    r.ny0 = -dy[0];
-    r.ny1 = -dy[1];
-    r.ny2 = -dy[2];
-    q.invA = 1.0f / (float)A;
-    q.rw0 = a.rw;
-    q.rw1 = b.rw;
-    q.rw2 = c.rw;
-    return mask | (notown << 16) | (fast ? 0u : kSlow);
+    x.hi0 = (int)(C[0] >> 32);
+    x.hi1 = (int)(C[1] >> 32);
+    x.hi2 = (int)(C[2] >> 32);
+    if (packed) {
+        r.e0 = (int)(((uint32_t)dx[0] & 0xFFFFu) | ((uint32_t)(-dy[0]) << 16));
+        r.e1 = (int)(((uint32_t)dx[1] & 0xFFFFu) | ((uint32_t)(-dy[1]) << 16));
+        r.e2 = (int)(((uint32_t)dx[2] & 0xFFFFu) | ((uint32_t)(-dy[2]) << 16));
+    } else {
+        r.e0 = dx[0];
+        r.e1 = dx[1];
+        r.e2 = dx[2];
+    }
+    x.ny0 = -dy[0];
+    x.ny1 = -dy[1];
+    x.ny2 = -dy[2];
+    r.invA = 1.0f / (float)A;
+    r.rw0 = a.rw;
+    r.rw1 = b.rw;
+    r.rw2 = c.rw;
+    r.key = key;
+    r.flags = mask | (notown << 16) | (fast ? 0u : kSlow) | (packed ? kPacked : 0u);
+    return r.flags;
 }
 
 __device__ __forceinline__ long long join64(int hi, int lo)
@@ -669,16 +767,17 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
     constexpr int NS = TS / 8;
     constexpr uint32_t cls = TS == 8 ? 0u : TS == 16 ? 1u : 2u;
     constexpr uint32_t S = kSegPerTile * NT;
-    __shared__ LCov scov[NT];
-    __shared__ LRho srho[NT];
+    __shared__ LRec srec[NT];
+    __shared__ LExt sext[NT];
     __shared__ uint32_t sflag[NT];
-    __shared__ uint32_t skeyl[NT];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int sx = (int)(wave % NS), sy = (int)(wave / NS);
     const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
     const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
+    // (Q, P) as a 16-bit pair for the packed edge records: dot2 gives dx Q - dy P
+    const short2_t QP = __builtin_bit_cast(short2_t, (uint32_t)Q | ((uint32_t)P << 16));
     const uint32_t total = q->total[cls];
     bool rerr = false;
 
@@ -714,8 +813,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
             {
                 const uint32_t e = base + tid;
                 uint32_t fl = 0, key = 0;
-                LCov r;
-                LRho rq;
+                LRec r;
+                LExt rx;
                 if (e < end) {
                     bool go = true;
                     if (over) {
@@ -727,59 +826,89 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
                     } else {
                         key = list[e];
                     }
-                    if (go) fl = build_rec<TS>(v, key, ti0, tj0, r, rq, rerr);
+                    if (go) fl = build_rec<TS>(v, key, ti0, tj0, r, rx, rerr);
                 }
                 sflag[tid] = fl;
                 if (fl) {
-                    scov[tid] = r;
-                    srho[tid] = rq;
-                    skeyl[tid] = key;
+                    srec[tid] = r;
+                    if (!(fl & kPacked)) sext[tid] = rx;
                 }
             }
             __syncthreads();
             const uint32_t m = min((uint32_t)NT, end - base);
+            // one visit: coverage of this wave's 64 pixels by record R (index
+            // k), then the key and the register z-test where covered
+            auto visit = [&](const LRec &R, uint32_t k) {
+                const uint32_t fl = R.flags;
+                const uint32_t nt = (fl >> 16) & 7u;
+                bool cov;
+                float w0, w1, w2;
+                if (fl & kPacked) {
+                    const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                    const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                    const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                    cov = (F0 | F1 | F2) >= 0;
+                    if (!__ballot(cov)) return;
+                    w0 = (float)(F0 + (int)(nt & 1u)) * R.rw0;
+                    w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * R.rw1;
+                    w2 = (float)(F2 + (int)(nt >> 2)) * R.rw2;
+                } else if (!(fl & kSlow)) {
+                    const LExt &X = sext[k];
+                    const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
+                    const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
+                    const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
+                    cov = (F0 | F1 | F2) >= 0;
+                    if (!__ballot(cov)) return;
+                    w0 = (float)(F0 + (int)(nt & 1u)) * R.rw0;
+                    w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * R.rw1;
+                    w2 = (float)(F2 + (int)(nt >> 2)) * R.rw2;
+                } else {
+                    const LExt &X = sext[k];
+                    const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
+                    const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
+                    const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
+                    cov = E0 >= (long long)(nt & 1u) && E1 >= (long long)((nt >> 1) & 1u) &&
+                          E2 >= (long long)(nt >> 2);
+                    if (!__ballot(cov)) return;
+                    w0 = (float)E0 * R.rw0;
+                    w1 = (float)E1 * R.rw1;
+                    w2 = (float)E2 * R.rw2;
+                }
+                const float num = (w0 + w1) + w2;
+                const float rho = num * R.invA;
+                const uint32_t key = R.key;
+                ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
+                const bool better = cov && (rho > best_rho || (rho == best_rho && key < best_key));
+                best_rho = better ? rho : best_rho;
+                best_key = better ? key : best_key;
+            };
             for (uint32_t g = 0; g < m; g += 64) {
                 // which of the next 64 records touch this wave's 8x8 sub-tile
                 const uint32_t f = (g + lane < m) ? sflag[g + lane] : 0u;
                 unsigned long long rel = __ballot((f >> wave) & 1u);
-                while (rel) {
-                    const int j = __ffsll((long long)rel) - 1;
-                    rel &= rel - 1ull;
-                    const uint32_t k = g + (uint32_t)j;
-                    const uint32_t fl = __shfl(f, j);
-                    const uint32_t nt = (fl >> 16) & 7u;
-                    const LCov &R = scov[k];
-                    bool cov;
-                    float w0, w1, w2;
-                    if (!(fl & kSlow)) {
-                        const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.dx0, Q) + (uint32_t)__mul24(R.ny0, P));
-                        const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.dx1, Q) + (uint32_t)__mul24(R.ny1, P));
-                        const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.dx2, Q) + (uint32_t)__mul24(R.ny2, P));
-                        cov = (F0 | F1 | F2) >= 0;
-                        if (!__ballot(cov)) continue;
-                        const LRho &Rq = srho[k];
-                        w0 = (float)(F0 + (int)(nt & 1u)) * Rq.rw0;
-                        w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * Rq.rw1;
-                        w2 = (float)(F2 + (int)(nt >> 2)) * Rq.rw2;
-                    } else {
-                        const long long E0 = join64(R.hi0, R.c0) + (long long)R.dx0 * Q + (long long)R.ny0 * P;
-                        const long long E1 = join64(R.hi1, R.c1) + (long long)R.dx1 * Q + (long long)R.ny1 * P;
-                        const long long E2 = join64(R.hi2, R.c2) + (long long)R.dx2 * Q + (long long)R.ny2 * P;
-                        cov = E0 >= (long long)(nt & 1u) && E1 >= (long long)((nt >> 1) & 1u) &&
-                              E2 >= (long long)(nt >> 2);
-                        if (!__ballot(cov)) continue;
-                        const LRho &Rq = srho[k];
-                        w0 = (float)E0 * Rq.rw0;
-                        w1 = (float)E1 * Rq.rw1;
-                        w2 = (float)E2 * Rq.rw2;
+                if (!rel) continue;
+                // two register sets take turns: the next relevant record is
+                // fetched while the current one is tested
+                uint32_t ka = g + (uint32_t)(__ffsll((long long)rel) - 1);
+                rel &= rel - 1ull;
+                LRec ra = srec[ka];
+                for (;;) {
+                    if (!rel) {
+                        visit(ra, ka);
+                        break;
                     }
-                    const float num = (w0 + w1) + w2;
-                    const float rho = num * srho[k].invA;
-                    const uint32_t key = skeyl[k];
-                    ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
-                    const bool better = cov && (rho > best_rho || (rho == best_rho && key < best_key));
-                    best_rho = better ? rho : best_rho;
-                    best_key = better ? key : best_key;
+                    const uint32_t kb = g + (uint32_t)(__ffsll((long long)rel) - 1);
+                    rel &= rel - 1ull;
+                    const LRec rb = srec[kb];
+                    visit(ra, ka);
+                    if (!rel) {
+                        visit(rb, kb);
+                        break;
+                    }
+                    ka = g + (uint32_t)(__ffsll((long long)rel) - 1);
+                    rel &= rel - 1ull;
+                    ra = srec[ka];
+                    visit(rb, kb);
                 }
             }
             __syncthreads();
@@ -889,9 +1018,9 @@ hipError_t launch_render(const LaunchPlan &L, hipStream_t s)
                        L.nviews, L.tile_count, L.tile_cursor, L.ntiles, L.queue);
     mark(L, 1, s);
     mark(L, 2, s);
-    if (L.setup_blocks)
-        hipLaunchKernelGGL(k_setup, dim3(L.setup_blocks), dim3(kSetupBlock), 0, s, L.views, L.groups,
-                           (int)L.ngroups, L.ctr, L.skey, L.sbox, L.err);
+    hipLaunchKernelGGL(k_cull, dim3(L.nviews), dim3(kScanBlock), 0, s, L.views, L.ctr, L.pairs);
+    hipLaunchKernelGGL(k_setup, dim3(L.setup_grid), dim3(kSetupBlock), 0, s, L.views, L.nviews, L.ctr,
+                       L.pairs, L.skey, L.sbox, L.err);
     mark(L, 3, s);
     mark(L, 4, s);
     hipLaunchKernelGGL(k_bin<false>, dim3(L.bin_grid), dim3(kBinBlock), 0, s, L.views, L.nviews,

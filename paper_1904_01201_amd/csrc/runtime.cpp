@@ -8,7 +8,6 @@
 
 namespace habmi {
 
-static constexpr uint32_t kGroupMax = 16;           // views per setup group
 static constexpr float kDefaultBinFactor = 2.0f;
 static constexpr uint32_t kDefaultTile = 16;
 static constexpr uint64_t kIndexLimit = 1ull << 31; // per launch: survivors, bins, tiles
@@ -192,9 +191,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
                      [&](uint32_t a, uint32_t b) { return v[a].scene < v[b].scene; });
 
     std::vector<DView> dv(n);
-    std::vector<DGroup> groups;
     std::vector<uint32_t> lview[3], lpre[3];
-    uint64_t tile_total = 0, surv_total = 0, bin_total = 0;
+    uint64_t tile_total = 0, surv_total = 0, bin_total = 0, pair_total = 0;
     for (uint32_t k = 0; k < n; ++k) {
         const ViewReq &r = v[plan.order[k]];
         float bf;
@@ -215,6 +213,7 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.pos = r.scene->pos;
         d.col = r.scene->col;
         d.idx = r.scene->idx;
+        d.cbox = r.scene->cbox;
         d.rgb = r.rgb;
         d.depth = r.depth;
         d.tri = r.tri;
@@ -232,6 +231,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.bin_cap = (uint32_t)bc;
         bin_total += bc;
         d.tile_cap = o.tile_cap ? o.tile_cap : 0xFFFFFFFFu;
+        d.pair_base = (uint32_t)pair_total;
+        pair_total += cdiv(d.T, kCluster);
         const int c = ts == 8 ? 0 : ts == 16 ? 1 : 2;
         lview[c].push_back(k);
     }
@@ -247,29 +248,16 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
             pre += dv[k].tiles_x * dv[k].tiles_y;
         }
     }
-    if (tile_total >= kIndexLimit || surv_total >= kIndexLimit || bin_total >= kIndexLimit)
+    if (tile_total >= kIndexLimit || surv_total >= kIndexLimit || bin_total >= kIndexLimit ||
+        pair_total >= kIndexLimit)
         return HAB_ERR_CAPACITY;
 
-    uint32_t setup_blocks = 0;
-    for (uint32_t k = 0; k < n;) {
-        uint32_t e = k + 1;
-        while (e < n && e - k < kGroupMax && v[plan.order[e]].scene == v[plan.order[k]].scene) ++e;
-        DGroup g;
-        g.first_view = k;
-        g.num_views = e - k;
-        g.T = dv[k].T;
-        g.block_start = setup_blocks;
-        setup_blocks += cdiv(g.T, kSetupBlock);
-        groups.push_back(g);
-        k = e;
-    }
+    const uint64_t npairs = pair_total;
 
     // descriptor block
     size_t off = 0;
     plan.off_views = off;
     off = align256(off + sizeof(DView) * n);
-    plan.off_groups = off;
-    off = align256(off + sizeof(DGroup) * groups.size());
     for (int c = 0; c < 3; ++c) {
         plan.off_lview[c] = off;
         off = align256(off + 4 * lview[c].size());
@@ -279,7 +267,7 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     plan.desc_bytes = off;
     desc.resize(off);
     std::memcpy(desc.data() + plan.off_views, dv.data(), sizeof(DView) * n);
-    std::memcpy(desc.data() + plan.off_groups, groups.data(), sizeof(DGroup) * groups.size());
+
     for (int c = 0; c < 3; ++c) {
         if (!lview[c].empty()) {
             std::memcpy(desc.data() + plan.off_lview[c], lview[c].data(), 4 * lview[c].size());
@@ -301,6 +289,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     off = align256(off + 8 * surv_total);
     plan.off_bins = off;
     off = align256(off + 4 * bin_total);
+    plan.off_pairs = off;
+    off = align256(off + 4 * std::max<uint64_t>(npairs, 1));
     plan.off_titem = off;
     off = align256(off + 4 * tile_total);
     plan.off_queue = off;
@@ -322,8 +312,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     LaunchPlan &L = plan.L;
     L = LaunchPlan{};
     L.nviews = n;
-    L.ngroups = (uint32_t)groups.size();
-    L.setup_blocks = setup_blocks;
+    L.setup_grid = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((npairs + 15) / 16, 8ull * (ctx ? ctx->cu_count : 256)));
     L.ntiles = (uint32_t)tile_total;
     uint64_t ub = 0;
     for (uint32_t k = 0; k < n; ++k) ub += cdiv(dv[k].surv_cap, kBinBlock * kBinItems);
@@ -351,7 +341,6 @@ void bind_plan(Plan &plan, void *arena, uint32_t *err)
     char *b = static_cast<char *>(arena);
     LaunchPlan &L = plan.L;
     L.views = reinterpret_cast<const DView *>(b + plan.off_views);
-    L.groups = reinterpret_cast<const DGroup *>(b + plan.off_groups);
     L.ctr = reinterpret_cast<DViewCounters *>(b + plan.off_ctr);
     L.tile_count = reinterpret_cast<uint32_t *>(b + plan.off_tcount);
     L.tile_off = reinterpret_cast<uint32_t *>(b + plan.off_toff);
@@ -361,6 +350,7 @@ void bind_plan(Plan &plan, void *arena, uint32_t *err)
     L.bins = reinterpret_cast<uint32_t *>(b + plan.off_bins);
     L.tile_item = reinterpret_cast<uint32_t *>(b + plan.off_titem);
     L.queue = reinterpret_cast<DQueue *>(b + plan.off_queue);
+    L.pairs = reinterpret_cast<uint32_t *>(b + plan.off_pairs);
     L.err = err;
     for (int c = 0; c < 3; ++c) L.items[c] = reinterpret_cast<uint2 *>(b + plan.off_items[c]);
     for (int k = 0; k < L.nraster; ++k) {
@@ -386,6 +376,7 @@ Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context
         const uint64_t S = (uint64_t)kSegPerTile * ts * ts;
         const uint64_t items = nt + (bc + S - 1) / S;
         bytes += 2ull * v[k].scene->T * 12ull + bc * 4ull + nt * 16ull + sizeof(DView) + 64 +
+                 4ull * cdiv(v[k].scene->T, kCluster) +
                  items * 8ull * (1 + (uint64_t)ts * ts);
     }
     f.desc_bytes = n * (sizeof(DView) + 32) + 4096;

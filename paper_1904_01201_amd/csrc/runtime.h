@@ -24,6 +24,7 @@ struct Scene {
     float *pos = nullptr;       // [V][3]
     uint32_t *col = nullptr;    // [V] packed
     uint32_t *idx = nullptr;    // [T][3]
+    float4 *cbox = nullptr;     // [ceil(T/64)][2] cluster bounding boxes
     uint32_t V = 0, T = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     uint64_t bytes = 0;
@@ -87,10 +88,11 @@ struct Plan {
     LaunchPlan L{};
     size_t desc_bytes = 0;
     size_t arena_bytes = 0;
-    size_t off_views = 0, off_groups = 0, off_lview[3] = {0, 0, 0}, off_lpre[3] = {0, 0, 0};
+    size_t off_views = 0, off_lview[3] = {0, 0, 0}, off_lpre[3] = {0, 0, 0};
     size_t off_ctr = 0, off_tcount = 0, off_toff = 0, off_tcur = 0;
     size_t off_skey = 0, off_sbox = 0, off_bins = 0;
     size_t off_titem = 0, off_queue = 0, off_items[3] = {0, 0, 0}, off_partial[3] = {0, 0, 0};
+    size_t off_pairs = 0;
     std::vector<uint32_t> order;     // sorted position -> caller index
     uint32_t n = 0;
 };
