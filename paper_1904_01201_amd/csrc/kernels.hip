@@ -580,15 +580,15 @@ __global__ __launch_bounds__(kScanBlock) void k_bin_scan(const DView *__restrict
 // LDS record of one (sub-triangle, tile) pair: edge functions relative to
 // the tile's first pixel centre, E_k(P, Q) = C_k + dx_k Q - dy_k P with
 // (P, Q) the pixel offset from that centre in 1/256 px.  Everything a visit
-// needs for the common (packed) case sits in one 48-byte block, read with
-// three 16-byte loads in one round trip; unpacked and int64 records keep
-// their extra words in a second array.
+// needs for the common (packed) case sits in one 48-byte block laid out as
+// three naturally aligned 16-byte words (three LDS loads); unpacked and
+// int64 records keep their extra words in a second array.
 struct alignas(16) LRec {
-    int c0, c1, c2;    // fast: C_k - notowned_k; slow: low words of C_k
-    int e0, e1, e2;    // packed: (dx_k, -dy_k) as 16-bit pairs; else dx_k
-    float rw0, rw1, rw2, invA;
-    uint32_t key;
+    int c0, c1, c2;    // C_k (slow: its low word)
     uint32_t flags;
+    int e0, e1, e2;    // packed: (dx_k, -dy_k) as 16-bit pairs; else dx_k
+    uint32_t nkey;     // ~key: the low word of the z-key
+    float rw0, rw1, rw2, invA;
 };
 struct alignas(16) LExt {
     int ny0, ny1, ny2; // -dy_k (unpacked records)
@@ -596,6 +596,27 @@ struct alignas(16) LExt {
     int pad0, pad1;
 };
 static_assert(sizeof(LRec) == 48 && sizeof(LExt) == 32, "LDS records");
+
+// One record as three 16-byte LDS loads.
+__device__ __forceinline__ LRec lds_rec(const LRec *base, uint32_t k)
+{
+    const uint4 *p = reinterpret_cast<const uint4 *>(base + k);
+    const uint4 a = p[0], b = p[1], c = p[2];
+    LRec r;
+    r.c0 = (int)a.x;
+    r.c1 = (int)a.y;
+    r.c2 = (int)a.z;
+    r.flags = a.w;
+    r.e0 = (int)b.x;
+    r.e1 = (int)b.y;
+    r.e2 = (int)b.z;
+    r.nkey = b.w;
+    r.rw0 = __uint_as_float(c.x);
+    r.rw1 = __uint_as_float(c.y);
+    r.rw2 = __uint_as_float(c.z);
+    r.invA = __uint_as_float(c.w);
+    return r;
+}
 
 // flags: bits 0..15 sub-tiles touched, 16..18 edge k not owned, 19 slow
 // (int64 edge values), 20 packed (every edge delta fits int16)
@@ -659,15 +680,9 @@ __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int 
     bool packed = fast;
 #pragma unroll
     for (int k = 0; k < 3; ++k) packed = packed && dx[k] < 32768 && dx[k] > -32768 && dy[k] < 32768 && dy[k] > -32768;
-    if (fast) {
-        r.c0 = (int)(C[0] - (long long)(notown & 1u));
-        r.c1 = (int)(C[1] - (long long)((notown >> 1) & 1u));
-        r.c2 = (int)(C[2] - (long long)((notown >> 2) & 1u));
-    } else {
-        r.c0 = (int)(uint32_t)(unsigned long long)C[0];
-        r.c1 = (int)(uint32_t)(unsigned long long)C[1];
-        r.c2 = (int)(uint32_t)(unsigned long long)C[2];
-    }
+    r.c0 = (int)(uint32_t)(unsigned long long)C[0];
+    r.c1 = (int)(uint32_t)(unsigned long long)C[1];
+    r.c2 = (int)(uint32_t)(unsigned long long)C[2];
     x.hi0 = (int)(C[0] >> 32);
     x.hi1 = (int)(C[1] >> 32);
     x.hi2 = (int)(C[2] >> 32);
@@ -687,7 +702,7 @@ __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int 
     r.rw0 = a.rw;
     r.rw1 = b.rw;
     r.rw2 = c.rw;
-    r.key = key;
+    r.nkey = ~key;
     r.flags = mask | (notown << 16) | (fast ? 0u : kSlow) | (packed ? kPacked : 0u);
     return r.flags;
 }
@@ -751,7 +766,9 @@ __device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int
 }
 
 template <int TS>
-__global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ views,
+// 6 waves per SIMD: the register budget (80 VGPRs) that lets enough
+// waves hide the LDS and staging latency; a 32-pixel tile's LDS allows 4.
+__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32 ? 4 : 6))) void k_raster(const DView *__restrict__ views,
                                                    const uint2 *__restrict__ items,
                                                    DQueue *__restrict__ q,
                                                    DViewCounters *__restrict__ ctr,
@@ -804,8 +821,11 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
         const uint32_t end = over ? ctr[vi].surv_count : min(begin + S, cnt);
         const uint32_t *list = bins + v.bin_base + (over ? 0u : off);
 
-        float best_rho = 0.0f;
-        uint32_t best_key = kNone;
+        // z-key of the best fragment so far: 1/w bits above the complemented
+        // triangle key.  A covered fragment has 1/w > 0 (positive weights,
+        // positive twice-area), so one unsigned max orders by largest 1/w,
+        // then smaller key; 0 means no fragment.
+        unsigned long long best = 0ull;
         uint32_t ncov = 0;
 
         for (uint32_t base = begin; base < end; base += NT) {
@@ -837,50 +857,53 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
             __syncthreads();
             const uint32_t m = min((uint32_t)NT, end - base);
             // one visit: coverage of this wave's 64 pixels by record R (index
-            // k), then the key and the register z-test where covered
+            // k) under the top-left rule (an edge not owned needs E > 0), then
+            // 1/w and the z-test where covered
             auto visit = [&](const LRec &R, uint32_t k) {
-                const uint32_t fl = R.flags;
-                const uint32_t nt = (fl >> 16) & 7u;
+                const uint32_t fl = __builtin_amdgcn_readfirstlane(R.flags);
+                const int n0 = (int)((fl >> 16) & 1u), n1 = (int)((fl >> 17) & 1u), n2 = (int)((fl >> 18) & 1u);
                 bool cov;
+                unsigned long long cm;
                 float w0, w1, w2;
                 if (fl & kPacked) {
                     const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
                     const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
                     const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
-                    cov = (F0 | F1 | F2) >= 0;
-                    if (!__ballot(cov)) return;
-                    w0 = (float)(F0 + (int)(nt & 1u)) * R.rw0;
-                    w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * R.rw1;
-                    w2 = (float)(F2 + (int)(nt >> 2)) * R.rw2;
+                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                    cm = __ballot(cov);
+                    if (!cm) return;
+                    w0 = (float)F0 * R.rw0;
+                    w1 = (float)F1 * R.rw1;
+                    w2 = (float)F2 * R.rw2;
                 } else if (!(fl & kSlow)) {
                     const LExt &X = sext[k];
                     const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
                     const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
                     const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
-                    cov = (F0 | F1 | F2) >= 0;
-                    if (!__ballot(cov)) return;
-                    w0 = (float)(F0 + (int)(nt & 1u)) * R.rw0;
-                    w1 = (float)(F1 + (int)((nt >> 1) & 1u)) * R.rw1;
-                    w2 = (float)(F2 + (int)(nt >> 2)) * R.rw2;
+                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                    cm = __ballot(cov);
+                    if (!cm) return;
+                    w0 = (float)F0 * R.rw0;
+                    w1 = (float)F1 * R.rw1;
+                    w2 = (float)F2 * R.rw2;
                 } else {
                     const LExt &X = sext[k];
                     const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
                     const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
                     const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
-                    cov = E0 >= (long long)(nt & 1u) && E1 >= (long long)((nt >> 1) & 1u) &&
-                          E2 >= (long long)(nt >> 2);
-                    if (!__ballot(cov)) return;
+                    cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
+                    cm = __ballot(cov);
+                    if (!cm) return;
                     w0 = (float)E0 * R.rw0;
                     w1 = (float)E1 * R.rw1;
                     w2 = (float)E2 * R.rw2;
                 }
                 const float num = (w0 + w1) + w2;
                 const float rho = num * R.invA;
-                const uint32_t key = R.key;
-                ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
-                const bool better = cov && (rho > best_rho || (rho == best_rho && key < best_key));
-                best_rho = better ? rho : best_rho;
-                best_key = better ? key : best_key;
+                const unsigned long long cand =
+                    ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
+                ncov += (uint32_t)__popcll(cm & inmask);
+                best = (cov && cand > best) ? cand : best;
             };
             for (uint32_t g = 0; g < m; g += 64) {
                 // which of the next 64 records touch this wave's 8x8 sub-tile
@@ -891,7 +914,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
                 // fetched while the current one is tested
                 uint32_t ka = g + (uint32_t)(__ffsll((long long)rel) - 1);
                 rel &= rel - 1ull;
-                LRec ra = srec[ka];
+                LRec ra = lds_rec(srec, ka);
                 for (;;) {
                     if (!rel) {
                         visit(ra, ka);
@@ -899,7 +922,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
                     }
                     const uint32_t kb = g + (uint32_t)(__ffsll((long long)rel) - 1);
                     rel &= rel - 1ull;
-                    const LRec rb = srec[kb];
+                    const LRec rb = lds_rec(srec, kb);
                     visit(ra, ka);
                     if (!rel) {
                         visit(rb, kb);
@@ -907,13 +930,13 @@ __global__ __launch_bounds__(TS *TS) void k_raster(const DView *__restrict__ vie
                     }
                     ka = g + (uint32_t)(__ffsll((long long)rel) - 1);
                     rel &= rel - 1ull;
-                    ra = srec[ka];
+                    ra = lds_rec(srec, ka);
                     visit(rb, kb);
                 }
             }
             __syncthreads();
         }
-        partial[(size_t)item * NT + tid] = make_uint2(__float_as_uint(best_rho), best_key);
+        partial[(size_t)item * NT + tid] = make_uint2((uint32_t)(best >> 32), ~(uint32_t)best);
         if (lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
     }
     if (rerr) atomicOr(err, kErrRange);
