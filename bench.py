@@ -39,6 +39,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measured_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth (bytes read + written per second),
+    timed with events on the current stream: the attainable HBM rate."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +137,15 @@ def main():
         set_poses(step)
         ctx.render_batch(None, views=views, tile_size=a.tile_size)
 
+    # ---------------------------------------------------- autotune (untimed)
+    tuned = None
+    if not a.tile_size:
+        t0 = time.perf_counter()
+        ts, bf = ctx.autotune(items0)
+        tuned = {"first_class_tile": ts, "first_class_bin_factor": bf}
+        log(f"autotune: tile {ts}, bin factor {bf} for the first batch class "
+            f"({time.perf_counter() - t0:.2f}s)")
+
     # ---------------------------------------------------- batched (eager)
     for s in range(a.warmup):
         batch_step(s)
@@ -173,24 +212,33 @@ def main():
     log(f"step latency p50 {p50:.3f} ms, p99 {p99:.3f} ms")
 
     # ---------------------------------------------------- work counters
-    set_poses(0)
-    stats = ctx.render_batch(None, views=views, tile_size=a.tile_size, stats=True)
-    bbox_tests = sum(s["bbox_tests"] for s in stats)
-    covered = sum(s["covered"] for s in stats)
-    survivors = sum(s["survivors"] for s in stats)
+    # the same poses as the timed steps, rendered again with counters on
+    bbox_tests = covered = survivors = 0
+    for s_ in range(a.steps):
+        set_poses(s_)
+        stats = ctx.render_batch(None, views=views, tile_size=a.tile_size, stats=True)
+        bbox_tests += sum(x["bbox_tests"] for x in stats)
+        covered += sum(x["covered"] for x in stats)
+        survivors += sum(x["survivors"] for x in stats)
+    bbox_tests //= a.steps
+    covered //= a.steps
+    survivors //= a.steps
     assert ctx.get_error() == 0
 
     # ---------------------------------------------------- roofline
-    raster = {k: v for k, v in phases.items() if k.startswith("raster")}
-    dom = max(phases.items(), key=lambda kv: kv[1]["ms"])[0]
     per_launch = {k: v["ms"] / max(v["launches"], 1) for k, v in phases.items()}
+    raster = [k for k in phases if k.startswith("raster")]
+    if raster:
+        # every raster launch of a step (one per tile size in use) together
+        per_launch["raster"] = sum(phases[k]["ms"] for k in raster) / max(phases[raster[0]]["launches"], 1)
+    dom = max(((k, v) for k, v in per_launch.items() if k not in raster), key=lambda kv: kv[1])[0]
     geom_bytes = sum(15 * s.num_vertices + 12 * s.num_triangles for s in w.scenes)
     out_bytes = E * 256 * 256 * 7
     step_bytes = out_bytes + geom_bytes + 48 * E
-    if dom.startswith("raster"):
+    if dom == "raster":
         ops = OPS_PER_TEST * bbox_tests + OPS_PER_COVERED * covered
         ach = ops / (per_launch[dom] * 1e-3) / 1e12
-        roof = {"kernel": f"k_raster<{dom[6:]}>", "bound": "alu", "achieved": round(ach, 4),
+        roof = {"kernel": "+".join(f"k_raster<{k[6:]}>" for k in raster), "bound": "alu", "achieved": round(ach, 4),
                 "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(ach / ALU_PEAK_TOPS, 5),
                 "traffic": None, "avg_launch_ms": round(per_launch[dom], 5),
                 "work_per_launch": {"bbox_tests": bbox_tests, "covered": covered,
@@ -202,10 +250,14 @@ def main():
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
                 "avg_launch_ms": round(per_launch[dom], 5)}
     ms_step = 1e3 * t_batch / a.steps
+    copy_gbs = measured_copy_gbs()
     hbm = {"algorithmic_bytes_per_step": step_bytes,
            "achieved_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 2),
            "peak_GBs": HBM_PEAK_GBS,
-           "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+           "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+           "measured_copy_GBs": round(copy_gbs, 1),
+           "frac_of_measured_copy": round(step_bytes / (ms_step * 1e-3) / 1e9 / copy_gbs, 5)}
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
 
     # ---------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -224,14 +276,22 @@ def main():
             sc = w.scenes[si]
             oracle.render_view(sc.positions, sc.colors, sc.indices, 256, 256, pose)
 
-        t0 = time.perf_counter()
+        t0, c0 = time.perf_counter(), time.process_time()
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(one, jobs))
-        t_cpu = time.perf_counter() - t0
+        t_cpu, c_cpu = time.perf_counter() - t0, time.process_time() - c0
+        n1 = min(len(jobs), E)
+        t0 = time.perf_counter()
+        for job in jobs[:n1]:
+            one(job)
+        t_one = time.perf_counter() - t0
         cpu = {"value": round(len(jobs) / t_cpu, 2), "unit": "frames/s", "cores": threads,
                "kind": "oracle",
                "sample": f"first {len(jobs)} views (steps 0..{(len(jobs) - 1) // E}) of the same "
-                         f"workload, one view per thread, {t_cpu:.1f}s wall"}
+                         f"workload, one view per thread, {t_cpu:.1f}s wall, {c_cpu:.1f} CPU-s",
+               "single_thread_value": round(n1 / t_one, 2),
+               "single_thread_sample": f"first {n1} views (step 0), one thread, {t_one:.1f}s",
+               "cpu_model": cpu_model()}
         log(f"cpu oracle: {cpu['value']} frames/s")
 
     res = {
@@ -250,7 +310,7 @@ def main():
         "config": {"workload": w.name, "envs": E, "scenes": len(w.scenes),
                    "triangles": [s.num_triangles for s in w.scenes], "resolution": [256, 256],
                    "outputs": "rgb+depth", "hfov_deg": 90.0, "path": "hab_render_batch",
-                   "tile_size": a.tile_size or "default"},
+                   "tile_size": a.tile_size or "autotuned", "autotune": tuned},
         "batched_fps": round(fps_batch, 1),
         "batched_graph_fps": round(fps_graph, 1),
         "per_view_fps": round(fps_pv, 1),

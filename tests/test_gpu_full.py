@@ -1,0 +1,137 @@
+"""Full-size workloads, in the launch configurations the benchmark times.
+
+The 64-environment batch (4 jittered apartments of 100k-1M triangles,
+256x256 RGB+D) is one hab_render_batch call per step with default options;
+the 256-environment mixed batch (16 apartments of 50k-1.5M triangles, 128/
+256/512 px, depth / RGB / RGB+D sensors) runs through the captured stepper.
+One view per environment every 50 steps of the 500-step walks is compared
+with the oracle (ids bit-exact, depth within 1e-5 relative, colour within
+1/255, work counters exact); every view is checked for what holds at any
+size; the stepper's replay must equal an eager batch bit for bit; the
+autotuner's choice must not change a bit.
+"""
+import numpy as np
+import pytest
+
+from scenegen import configs
+from tests.gpu_common import check_any_size, gpu_ctx, note, oracle_compare_many, to_np
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE_STEPS = range(0, 500, 50)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gpu_ctx()
+    yield c
+    c.close()
+
+
+def test_batch64_sampled_steps(ctx):
+    import torch
+    note("batch64_4scenes_256: hab_render_batch, every 50th step vs oracle")
+    w = configs.batch64_4scenes_256(steps=500)
+    hs = [ctx.upload_scene(s) for s in w.scenes]
+    sn = ctx.sensor(256, 256)
+    out = ctx.alloc(sn, w.num_envs, tri=True)
+    views = 0
+    for step in SAMPLE_STEPS:
+        note(f"batch64 step {step}")
+        items = [(hs[w.env_scene[e]], sn, w.poses[step, e], out["rgb"][e], out["depth"][e],
+                  out["tri"][e]) for e in range(w.num_envs)]
+        stats = ctx.render_batch(items, stats=True)
+        torch.cuda.synchronize()
+        g = to_np(out)
+        jobs = []
+        for e in range(w.num_envs):
+            sc = w.scenes[w.env_scene[e]]
+            ge = {k: v[e] for k, v in g.items()}
+            check_any_size(ge, sc.num_triangles, f"step {step} env {e}")
+            jobs.append((sc, w.env_sensor[e], w.poses[step, e], ge, stats[e], f"step {step} env {e}"))
+        views += oracle_compare_many(jobs)
+    note(f"batch64: {views} views match the oracle")
+    for h in hs:
+        ctx.release(h)
+
+
+def test_mixed256_stepper_sampled_steps(ctx):
+    import torch
+    note("batch256_16scenes_mixed: stepper, every 50th step vs oracle")
+    w = configs.batch256_16scenes_mixed(steps=500)
+    hs = [ctx.upload_scene(s) for s in w.scenes]
+    sensors = {}
+    for s in w.env_sensor:
+        key = (s.width, s.outputs)
+        if key not in sensors:
+            sensors[key] = ctx.sensor(s.width, s.height, s.hfov_deg, s.near_m, s.outputs)
+    env_sn = [sensors[(s.width, s.outputs)] for s in w.env_sensor]
+
+    def make_items(step):
+        outs = [ctx.alloc(env_sn[e], 1, tri=True) for e in range(w.num_envs)]
+        items = [(hs[w.env_scene[e]], env_sn[e], w.poses[step, e], outs[e].get("rgb"),
+                  outs[e].get("depth"), outs[e]["tri"]) for e in range(w.num_envs)]
+        return outs, items
+
+    outs_g, items_g = make_items(0)
+    st = ctx.stepper(items_g)
+    views = 0
+    for n, step in enumerate(SAMPLE_STEPS):
+        note(f"mixed256 step {step}")
+        st.step(w.poses[step])
+        torch.cuda.synchronize()
+        if n == 0:
+            outs_e, items_e = make_items(step)
+            ctx.render_batch(items_e)
+            torch.cuda.synchronize()
+            for e in range(w.num_envs):
+                for k in outs_g[e]:
+                    assert torch.equal(outs_g[e][k], outs_e[e][k]), (e, k)
+            del outs_e, items_e
+        g = [{k: v[0] for k, v in to_np(o).items()} for o in outs_g]
+        jobs = []
+        for e in range(w.num_envs):
+            sc = w.scenes[w.env_scene[e]]
+            check_any_size(g[e], sc.num_triangles, f"step {step} env {e}")
+            jobs.append((sc, w.env_sensor[e], w.poses[step, e], g[e], None, f"step {step} env {e}"))
+        views += oracle_compare_many(jobs)
+    note(f"mixed256: {views} views match the oracle")
+    st.close()
+    for h in hs:
+        ctx.release(h)
+
+
+def test_autotune_choice_and_invariance():
+    """The autotuner picks a tile size and bin factor from its candidate
+    sets, later default calls use them, and the output stays bit-identical
+    to a fixed 16-pixel tiling."""
+    import torch
+    import paper_1904_01201_amd as P
+    note("autotune")
+    c = gpu_ctx()
+    try:
+        w = configs.batch64_4scenes_256(steps=2, scene_T=(20_000, 120_000))
+        hs = [c.upload_scene(s) for s in w.scenes]
+        sn = c.sensor(256, 256)
+        ref = c.alloc(sn, w.num_envs, tri=True)
+        items = [(hs[w.env_scene[e]], sn, w.poses[1, e], ref["rgb"][e], ref["depth"][e], ref["tri"][e])
+                 for e in range(w.num_envs)]
+        c.render_batch(items, tile_size=16)
+        ts, bf = c.autotune(items)
+        assert ts in (8, 16, 32) and bf in (1.0, 2.0, 4.0), (ts, bf)
+        got = c.alloc(sn, w.num_envs, tri=True)
+        items2 = [(it[0], it[1], it[2], got["rgb"][e], got["depth"][e], got["tri"][e])
+                  for e, it in enumerate(items)]
+        c.profile(True)
+        c.render_batch(items2)
+        c.profile(False)
+        phases = c.profile_read()
+        assert f"raster{ts}" in phases, (ts, sorted(phases))
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(ref[k], got[k]), k
+        assert c.get_error() == P.HAB_OK
+        for h in hs:
+            c.release(h)
+    finally:
+        c.close()

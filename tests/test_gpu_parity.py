@@ -95,11 +95,11 @@ def test_random_tiny_scenes(ctx, seed):
 
 
 def test_apartment_sampled_walk(ctx):
-    """apartment_200k_256: every 100th pose of the 1,000-step walk."""
+    """apartment_200k_256: every 10th pose of the 1,000-step walk."""
     note("apartment_200k_256 sample")
     w = configs.apartment_200k_256()
     sc = w.scenes[0]
-    poses = w.poses[::100, 0]
+    poses = w.poses[::10, 0]
     check_views(ctx, sc.positions, sc.colors, sc.indices, 256, 256, poses, what="apartment")
 
 

@@ -109,3 +109,65 @@ def test_ticket_semantics(env):
     with pytest.raises(P.HabError):
         srv.poll(10 ** 9)
     srv.close()
+
+
+def test_served_full_scale():
+    """serve_32scenes at full size: 32 resident apartments (about 20M
+    triangles), 512 agents with mixed sensors, four steps; each agent has at
+    most one request in flight.  Every result is checked for what holds at
+    any size (on the device); 1% of the requests are compared with the
+    oracle."""
+    import torch
+    import paper_1904_01201_amd as P
+    from tests.gpu_common import NONE, check_any_size, oracle_compare_many, to_np
+    note("server: serve_32scenes full scale")
+    w = configs.serve_32scenes(num_agents=512, steps=4)
+    ctx = gpu_ctx()
+    try:
+        hs = [ctx.upload_scene(s) for s in w.scenes]
+        sensors = {}
+        for s in w.env_sensor:
+            if (s.width, s.outputs) not in sensors:
+                sensors[(s.width, s.outputs)] = ctx.sensor(s.width, s.height, s.hfov_deg, s.near_m,
+                                                           s.outputs)
+        srv = P.Server(ctx, num_streams=4, max_batch=256)
+        rng = np.random.default_rng(11)
+        total = w.num_steps * w.num_envs
+        sample = set(rng.choice(total, size=max(1, total // 100), replace=False).tolist())
+        jobs = []
+        for step in range(w.num_steps):
+            note(f"serve full scale: step {step}")
+            reqs = []
+            for e in range(w.num_envs):
+                sn = sensors[(w.env_sensor[e].width, w.env_sensor[e].outputs)]
+                out = ctx.alloc(sn, 1, tri=True)
+                t = srv.submit(hs[w.env_scene[e]], sn, w.poses[step, e], out.get("rgb"), out.get("depth"),
+                               out["tri"])
+                reqs.append((e, t, out))
+            for e, t, out in reqs:
+                srv.wait(t)
+            torch.cuda.synchronize()
+            for e, t, out in reqs:
+                tri = out["tri"].view(torch.int32)
+                miss = tri == -1
+                assert int(tri[~miss].max().item() if (~miss).any() else 0) < w.scenes[w.env_scene[e]].num_triangles
+                if "depth" in out:
+                    d = out["depth"]
+                    assert not bool((d[miss] != 0).any()), (step, e)
+                    assert bool((d[~miss] > 0).all()), (step, e)
+                if "rgb" in out:
+                    assert not bool((out["rgb"][miss] != 0).any()), (step, e)
+                if step * w.num_envs + e in sample:
+                    g = {k: v[0] for k, v in to_np(out).items()}
+                    sc = w.scenes[w.env_scene[e]]
+                    check_any_size(g, sc.num_triangles, f"served step {step} env {e}")
+                    jobs.append((sc, w.env_sensor[e], w.poses[step, e], g, None, f"served step {step} env {e}"))
+        st = srv.stats()
+        srv.close()
+        assert st["completed"] == total and st["rejected"] == 0
+        assert oracle_compare_many(jobs) == len(sample)
+        assert ctx.get_error() == P.HAB_OK
+        for h in hs:
+            ctx.release(h)
+    finally:
+        ctx.close()
