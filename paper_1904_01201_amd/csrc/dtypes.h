@@ -40,7 +40,8 @@ struct alignas(16) DView {
     uint32_t tile_cap;          // entries one tile may hold (else overflow)
     uint32_t pair_base;         // first entry of this view's visible-cluster segment
     const float4 *cbox;         // per 64-triangle cluster: (min xyz, -) (max xyz, -)
-    uint32_t pad[2];
+    uint32_t count_work;        // 1: accumulate bbox tests and covered fragments
+    uint32_t pad;
 };
 static_assert(sizeof(DView) == 192, "DView layout");
 
@@ -53,13 +54,17 @@ struct DQueue {
 };
 
 // Per-view counters (zeroed at the start of every launch sequence).
-struct DViewCounters {
+// Each view's counters sit on a cache line of their own, so the atomics of
+// different views never meet on one line.
+struct alignas(128) DViewCounters {
     uint32_t surv_count;        // survivors appended by setup
     uint32_t bin_used;          // entries the scan assigned
     uint32_t vis_clusters;      // clusters that passed the view's frustum test
     uint32_t pad;
     unsigned long long bbox_tests;
     unsigned long long covered;
+    uint32_t pad2[24];
 };
+static_assert(sizeof(DViewCounters) == 128, "counter line");
 
 }  // namespace habmi

@@ -316,14 +316,9 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
         }
         bool s[kRun][2];
         PixBox bx[kRun][2];
-        uint32_t area = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < kRun; ++j) {
+        for (uint32_t j = 0; j < kRun; ++j)
             survive(v, P[j], valid[j], s[j][0], s[j][1], bx[j][0], bx[j][1], rerr);
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-                if (s[j][q]) area += (uint32_t)(bx[j][q].i1 - bx[j][q].i0 + 1) * (uint32_t)(bx[j][q].j1 - bx[j][q].j0 + 1);
-        }
         // slots in (cluster, sub, lane) order
         uint32_t cnt = 0, mine[kRun][2];
 #pragma unroll
@@ -335,14 +330,21 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
                 cnt += (uint32_t)__popcll(m);
             }
         if (!cnt) continue;
-        // eight boxes of at most 2^24 pixels per lane: the two halves of
-        // the wave sum cannot overflow
-        const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
-        const uint32_t ahi = wave_sum_u32(area >> 16);
         uint32_t base = 0;
-        if (lane == 0) {
-            base = atomicAdd(&ctr[vi].surv_count, cnt);
-            atomicAdd(&ctr[vi].bbox_tests, (unsigned long long)alo + ((unsigned long long)ahi << 16));
+        if (lane == 0) base = atomicAdd(&ctr[vi].surv_count, cnt);
+        if (v.count_work) {
+            uint32_t area = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < kRun; ++j)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (s[j][q])
+                        area += (uint32_t)(bx[j][q].i1 - bx[j][q].i0 + 1) * (uint32_t)(bx[j][q].j1 - bx[j][q].j0 + 1);
+            // eight boxes of at most 2^24 pixels per lane: the two halves
+            // of the wave sum cannot overflow
+            const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
+            const uint32_t ahi = wave_sum_u32(area >> 16);
+            if (lane == 0) atomicAdd(&ctr[vi].bbox_tests, (unsigned long long)alo + ((unsigned long long)ahi << 16));
         }
         base = __shfl(base, 0) + v.surv_base;
 #pragma unroll
@@ -937,7 +939,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             __syncthreads();
         }
         partial[(size_t)item * NT + tid] = make_uint2((uint32_t)(best >> 32), ~(uint32_t)best);
-        if (lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
+        if (v.count_work && lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
     }
     if (rerr) atomicOr(err, kErrRange);
 }

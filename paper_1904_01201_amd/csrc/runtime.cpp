@@ -231,6 +231,7 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.bin_cap = (uint32_t)bc;
         bin_total += bc;
         d.tile_cap = o.tile_cap ? o.tile_cap : 0xFFFFFFFFu;
+        d.count_work = o.count_work ? 1u : 0u;
         d.pair_base = (uint32_t)pair_total;
         pair_total += cdiv(d.T, kCluster);
         const int c = ts == 8 ? 0 : ts == 16 ? 1 : 2;
@@ -375,7 +376,7 @@ Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context
         uint64_t bc = std::max<uint64_t>((uint64_t)std::ceil((double)bf * v[k].scene->T), 1024);
         const uint64_t S = (uint64_t)kSegPerTile * ts * ts;
         const uint64_t items = nt + (bc + S - 1) / S;
-        bytes += 2ull * v[k].scene->T * 12ull + bc * 4ull + nt * 16ull + sizeof(DView) + 64 +
+        bytes += 2ull * v[k].scene->T * 12ull + bc * 4ull + nt * 16ull + sizeof(DView) + sizeof(DViewCounters) + 64 +
                  4ull * cdiv(v[k].scene->T, kCluster) +
                  items * 8ull * (1 + (uint64_t)ts * ts);
     }
@@ -387,8 +388,10 @@ Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context
 
 // ---------------------------------------------------------------- launching
 hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
-                        const PlanOpts &o, hipStream_t s, hab_view_stats *stats)
+                        const PlanOpts &opts, hipStream_t s, hab_view_stats *stats)
 {
+    PlanOpts o = opts;
+    o.count_work = stats != nullptr;
     Plan plan;
     hab_status st = build_plan(ctx, ws, v, n, o, plan, ws.desc);
     if (st != HAB_OK) return st;

@@ -44,6 +44,7 @@ struct PlanOpts {
     uint32_t tile_size = 0;     // 0: per-class autotuned choice, else default
     float bin_factor = 0.0f;    // 0: default
     uint32_t tile_cap = 0;      // 0: unlimited
+    bool count_work = false;    // accumulate bbox tests / covered fragments
 };
 
 // Sizes of one launch sequence; used for memory admission as well.
