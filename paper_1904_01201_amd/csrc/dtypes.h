@@ -45,12 +45,21 @@ struct alignas(16) DView {
 };
 static_assert(sizeof(DView) == 192, "DView layout");
 
-// Work queues of the raster stage, one per tile size (8, 16, 32): `total`
-// items were appended by the scan, `head` is the next one to hand out.
-struct DQueue {
-    uint32_t head[4];
+// Work queues of the raster stage, per tile size (8, 16, 32): `total`
+// items were appended by the scan.  The items are dealt to kQueues queues
+// in interleaved groups of kQueueGroup; each queue's head sits on its own
+// cache line, so the blocks that drain different queues never contend for
+// one atomic.
+constexpr uint32_t kQueues = 8;       // one per XCD when blocks are dealt round-robin
+constexpr uint32_t kQueueGroup = 4;   // consecutive items that go to one queue
+struct alignas(128) DQueueHead {
+    uint32_t next;
+    uint32_t pad[31];
+};
+struct alignas(128) DQueue {
     uint32_t total[4];
-    uint32_t pad[4];
+    uint32_t pad[28];
+    DQueueHead head[3][kQueues];
 };
 
 // Per-view counters (zeroed at the start of every launch sequence).

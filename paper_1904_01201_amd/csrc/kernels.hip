@@ -139,10 +139,8 @@ __global__ __launch_bounds__(256) void k_reset(DViewCounters *__restrict__ ctr, 
         tile_count[i] = 0;
         tile_cursor[i] = 0;
     }
-    if (i < 4) {
-        q->head[i] = 0;
-        q->total[i] = 0;
-    }
+    if (i < 4) q->total[i] = 0;
+    if (i < 3 * kQueues) q->head[i / kQueues][i % kQueues].next = 0;
 }
 
 // ------------------------------------------------------------ k_setup
@@ -800,8 +798,15 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     const uint32_t total = q->total[cls];
     bool rerr = false;
 
+    // nq queues (at most one per block); this block drains queue x, whose
+    // k-th grab is item ((k / G) nq + x) G + k % G with G = kQueueGroup:
+    // every item belongs to exactly one (queue, grab), in increasing order
+    const uint32_t nq = min(kQueues, gridDim.x), x = blockIdx.x % nq;
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&q->head[cls], 1u);
+        if (tid == 0) {
+            const uint32_t k = atomicAdd(&q->head[cls][x].next, 1u);
+            s_item = ((k / kQueueGroup) * nq + x) * kQueueGroup + k % kQueueGroup;
+        }
         __syncthreads();
         const uint32_t item = s_item;
         __syncthreads();
