@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dtypes.h"
 #include "kernels.h"
 #include "raster_math.h"
@@ -618,16 +620,21 @@ __device__ __forceinline__ LRec lds_rec(const LRec *base, uint32_t k)
     return r;
 }
 
-// flags: bits 0..15 sub-tiles touched, 16..18 edge k not owned, 19 slow
-// (int64 edge values), 20 packed (every edge delta fits int16)
+// flags: bits 16..18 edge k not owned, 19 slow (int64 edge values), 20
+// packed (every edge delta fits int16)
 constexpr uint32_t kSlow = 1u << 19;
 constexpr uint32_t kPacked = 1u << 20;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
+// Mask of the tile's 4x4-pixel quarters (row-major, TS/4 per row) that a
+// record's pixel box touches: 4, 16 or 64 bits.
 template <int TS>
-__device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int ti0, int tj0,
-                                              LRec &r, LExt &x, bool &rerr)
+using QMask = typename std::conditional<TS == 32, unsigned long long, uint32_t>::type;
+
+template <int TS>
+__device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0, int tj0, LRec &r, LExt &x,
+                                          QMask<TS> &qm, bool &rerr)
 {
     const uint32_t t = key >> 1;
     const int sub = (int)(key & 1u);
@@ -640,19 +647,19 @@ __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int 
     cam_xform(v, P[6], P[7], P[8], c2);
     SVtx<0> a, b, c;
     long long A;
-    if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) return 0;
+    if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) return false;
     const PixBox pb = pix_box(v, a, b, c);
     const int bi0 = max(pb.i0 - ti0, 0), bi1 = min(pb.i1 - ti0, TS - 1);
     const int bj0 = max(pb.j0 - tj0, 0), bj1 = min(pb.j1 - tj0, TS - 1);
-    if (bi0 > bi1 || bj0 > bj1) return 0;
-    constexpr int NS = TS / 8;
-    uint32_t mask = 0;
-    const int sx0 = bi0 >> 3, sx1 = bi1 >> 3, sy0 = bj0 >> 3, sy1 = bj1 >> 3;
+    if (bi0 > bi1 || bj0 > bj1) return false;
+    constexpr int NQ = TS / 4;
+    using Q = QMask<TS>;
+    const int qx0 = bi0 >> 2, qx1 = bi1 >> 2, qy0 = bj0 >> 2, qy1 = bj1 >> 2;
+    const Q row = (Q)(((Q)2 << qx1) - ((Q)1 << qx0));
+    qm = 0;
 #pragma unroll
-    for (int sy = 0; sy < NS; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < NS; ++sx)
-            if (sx >= sx0 && sx <= sx1 && sy >= sy0 && sy <= sy1) mask |= 1u << (sy * NS + sx);
+    for (int qy = 0; qy < NQ; ++qy)
+        if (qy >= qy0 && qy <= qy1) qm |= row << (qy * NQ);
 
     // edge k runs from vertex k+1 to vertex k+2
     const int dx[3] = {c.X - b.X, a.X - c.X, b.X - a.X};
@@ -703,8 +710,8 @@ __device__ __forceinline__ uint32_t build_rec(const DView &v, uint32_t key, int 
     r.rw1 = b.rw;
     r.rw2 = c.rw;
     r.nkey = ~key;
-    r.flags = mask | (notown << 16) | (fast ? 0u : kSlow) | (packed ? kPacked : 0u);
-    return r.flags;
+    r.flags = (notown << 16) | (fast ? 0u : kSlow) | (packed ? kPacked : 0u);
+    return true;
 }
 
 __device__ __forceinline__ long long join64(int hi, int lo)
@@ -784,9 +791,11 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     constexpr int NS = TS / 8;
     constexpr uint32_t cls = TS == 8 ? 0u : TS == 16 ? 1u : 2u;
     constexpr uint32_t S = kSegPerTile * NT;
+    constexpr int NQ = TS / 4;
+    using QM = QMask<TS>;
     __shared__ LRec srec[NT];
     __shared__ LExt sext[NT];
-    __shared__ uint32_t sflag[NT];
+    __shared__ QM sqm[NT];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -839,11 +848,12 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             // stage: each thread rebuilds one list entry's edge setup for this tile
             {
                 const uint32_t e = base + tid;
-                uint32_t fl = 0, key = 0;
+                QM qm = 0;
                 LRec r;
                 LExt rx;
                 if (e < end) {
                     bool go = true;
+                    uint32_t key;
                     if (over) {
                         const uint2 bb = sbox[v.surv_base + e];
                         const int i0 = (int)(bb.x & 0xFFFFu), j0 = (int)(bb.x >> 16);
@@ -853,58 +863,19 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     } else {
                         key = list[e];
                     }
-                    if (go) fl = build_rec<TS>(v, key, ti0, tj0, r, rx, rerr);
+                    if (go && !build_rec<TS>(v, key, ti0, tj0, r, rx, qm, rerr)) qm = 0;
                 }
-                sflag[tid] = fl;
-                if (fl) {
+                sqm[tid] = qm;
+                if (qm) {
                     srec[tid] = r;
-                    if (!(fl & kPacked)) sext[tid] = rx;
+                    if (!(r.flags & kPacked)) sext[tid] = rx;
                 }
             }
             __syncthreads();
             const uint32_t m = min((uint32_t)NT, end - base);
-            // one visit: coverage of this wave's 64 pixels by record R (index
-            // k) under the top-left rule (an edge not owned needs E > 0), then
-            // 1/w and the z-test where covered
-            auto visit = [&](const LRec &R, uint32_t k) {
-                const uint32_t fl = __builtin_amdgcn_readfirstlane(R.flags);
-                const int n0 = (int)((fl >> 16) & 1u), n1 = (int)((fl >> 17) & 1u), n2 = (int)((fl >> 18) & 1u);
-                bool cov;
-                unsigned long long cm;
-                float w0, w1, w2;
-                if (fl & kPacked) {
-                    const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
-                    const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
-                    const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
-                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
-                    cm = __ballot(cov);
-                    if (!cm) return;
-                    w0 = (float)F0 * R.rw0;
-                    w1 = (float)F1 * R.rw1;
-                    w2 = (float)F2 * R.rw2;
-                } else if (!(fl & kSlow)) {
-                    const LExt &X = sext[k];
-                    const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
-                    const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
-                    const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
-                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
-                    cm = __ballot(cov);
-                    if (!cm) return;
-                    w0 = (float)F0 * R.rw0;
-                    w1 = (float)F1 * R.rw1;
-                    w2 = (float)F2 * R.rw2;
-                } else {
-                    const LExt &X = sext[k];
-                    const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
-                    const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
-                    const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
-                    cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
-                    cm = __ballot(cov);
-                    if (!cm) return;
-                    w0 = (float)E0 * R.rw0;
-                    w1 = (float)E1 * R.rw1;
-                    w2 = (float)E2 * R.rw2;
-                }
+            // z-test of this lane's pixel against fragment weights w_k where
+            // covered (cov) and the wave's coverage ballot cm
+            auto zkeep = [&](const LRec &R, bool cov, unsigned long long cm, float w0, float w1, float w2) {
                 const float num = (w0 + w1) + w2;
                 const float rho = num * R.invA;
                 const unsigned long long cand =
@@ -912,33 +883,75 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                 ncov += (uint32_t)__popcll(cm & inmask);
                 best = (cov && cand > best) ? cand : best;
             };
+            // one step: every active lane tests its pixel against record R
+            // (index k) of its quarter under the top-left rule (an edge not
+            // owned needs E > 0)
+            auto visit = [&](const LRec &R, uint32_t k, bool act) {
+                const uint32_t fl = R.flags;
+                const int n0 = (int)((fl >> 16) & 1u), n1 = (int)((fl >> 17) & 1u), n2 = (int)((fl >> 18) & 1u);
+                if (!__ballot(act && !(fl & kPacked))) {
+                    // every active lane's record is packed
+                    const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                    const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                    const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                    const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
+                    const unsigned long long cm = __ballot(cov);
+                    if (!cm) return;
+                    zkeep(R, cov, cm, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
+                    return;
+                }
+                bool cov = false;
+                float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+                if (act && (fl & kPacked)) {
+                    const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                    const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                    const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                    w0 = (float)F0 * R.rw0;
+                    w1 = (float)F1 * R.rw1;
+                    w2 = (float)F2 * R.rw2;
+                } else if (act && !(fl & kSlow)) {
+                    const LExt &X = sext[k];
+                    const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
+                    const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
+                    const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
+                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                    w0 = (float)F0 * R.rw0;
+                    w1 = (float)F1 * R.rw1;
+                    w2 = (float)F2 * R.rw2;
+                } else if (act) {
+                    const LExt &X = sext[k];
+                    const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
+                    const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
+                    const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
+                    cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
+                    w0 = (float)E0 * R.rw0;
+                    w1 = (float)E1 * R.rw1;
+                    w2 = (float)E2 * R.rw2;
+                }
+                const unsigned long long cm = __ballot(cov);
+                if (!cm) return;
+                zkeep(R, cov, cm, w0, w1, w2);
+            };
+            // the wave's four 16-lane quarters (4x4 pixels each) walk their
+            // own lists of records whose box touches them: one step tests up
+            // to four records.  Bits qb, qb+1, qb+NQ, qb+NQ+1 of a record's
+            // quarter mask are this wave's quarters.
+            const uint32_t qb = (uint32_t)(2 * sy * NQ + 2 * sx);
+            const uint32_t lq = ((lane >> 5) << 1) | ((lane >> 2) & 1u);
             for (uint32_t g = 0; g < m; g += 64) {
-                // which of the next 64 records touch this wave's 8x8 sub-tile
-                const uint32_t f = (g + lane < m) ? sflag[g + lane] : 0u;
-                unsigned long long rel = __ballot((f >> wave) & 1u);
-                if (!rel) continue;
-                // two register sets take turns: the next relevant record is
-                // fetched while the current one is tested
-                uint32_t ka = g + (uint32_t)(__ffsll((long long)rel) - 1);
-                rel &= rel - 1ull;
-                LRec ra = lds_rec(srec, ka);
-                for (;;) {
-                    if (!rel) {
-                        visit(ra, ka);
-                        break;
-                    }
-                    const uint32_t kb = g + (uint32_t)(__ffsll((long long)rel) - 1);
-                    rel &= rel - 1ull;
-                    const LRec rb = lds_rec(srec, kb);
-                    visit(ra, ka);
-                    if (!rel) {
-                        visit(rb, kb);
-                        break;
-                    }
-                    ka = g + (uint32_t)(__ffsll((long long)rel) - 1);
-                    rel &= rel - 1ull;
-                    ra = lds_rec(srec, ka);
-                    visit(rb, kb);
+                const QM qm = (g + lane < m) ? sqm[g + lane] : (QM)0;
+                const unsigned long long m0 = __ballot((qm >> qb) & 1u);
+                const unsigned long long m1 = __ballot((qm >> (qb + 1)) & 1u);
+                const unsigned long long m2 = __ballot((qm >> (qb + NQ)) & 1u);
+                const unsigned long long m3 = __ballot((qm >> (qb + NQ + 1)) & 1u);
+                if (!(m0 | m1 | m2 | m3)) continue;
+                unsigned long long mine = lq == 0 ? m0 : lq == 1 ? m1 : lq == 2 ? m2 : m3;
+                while (__ballot(mine != 0ull)) {
+                    const bool act = mine != 0ull;
+                    const uint32_t k = g + (act ? (uint32_t)(__ffsll((long long)mine) - 1) : 0u);
+                    mine &= mine - 1ull;
+                    visit(lds_rec(srec, k), k, act);
                 }
             }
             __syncthreads();
