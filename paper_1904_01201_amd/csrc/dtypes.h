@@ -63,17 +63,19 @@ struct alignas(128) DQueue {
 };
 
 // Per-view counters (zeroed at the start of every launch sequence).
-// Each view's counters sit on a cache line of their own, so the atomics of
-// different views never meet on one line.
+// Each view's counters take two cache lines: the first holds what atomics
+// update, the second what is written once and read by many waves, so
+// those reads never queue behind the atomics (nor do different views'
+// atomics meet on one line).
 struct alignas(128) DViewCounters {
     uint32_t surv_count;        // survivors appended by setup
     uint32_t bin_used;          // entries the scan assigned
-    uint32_t vis_clusters;      // clusters that passed the view's frustum test
-    uint32_t pad;
     unsigned long long bbox_tests;
     unsigned long long covered;
-    uint32_t pad2[24];
+    uint32_t pad[26];
+    uint32_t vis_clusters;      // clusters that passed the view's frustum test
+    uint32_t pad2[31];
 };
-static_assert(sizeof(DViewCounters) == 128, "counter line");
+static_assert(sizeof(DViewCounters) == 256, "counter lines");
 
 }  // namespace habmi

@@ -250,12 +250,14 @@ __global__ __launch_bounds__(kScanBlock) void k_cull(const DView *__restrict__ v
 }
 
 // Work items of k_setup: (view, run of kRun visible clusters).  Each block
-// builds the prefix of item counts over the views in LDS, then its waves
-// stride over the items.  A wave sets up one triangle of each of the run's
-// clusters per lane (independent loads in flight together), keeps the
-// survivors in registers, reserves their slots with one atomic and writes
-// them with their boxes.
+// builds the prefix of item counts over the views in LDS; each wave then
+// takes a contiguous range of items.  A wave sets up one triangle of each
+// of the run's clusters per lane (independent loads in flight together),
+// appends the survivors (key, box) to its LDS buffer, and copies the buffer
+// out behind one slot reservation when the view changes or the buffer is
+// full: device-wide atomics, not the arithmetic, bound this stage.
 constexpr uint32_t kRun = 4;
+constexpr uint32_t kSetupBuf = 2 * kRun * kCluster;   // survivors one wave buffers in LDS
 
 __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__ views,
                                                        uint32_t nviews,
@@ -267,6 +269,8 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
 {
     __shared__ uint32_t pre[kMaxViews];
     __shared__ uint32_t wtot[kSetupBlock / 64];
+    __shared__ uint32_t bkey[kSetupBlock / 64][kSetupBuf];
+    __shared__ uint2 bbox[kSetupBlock / 64][kSetupBuf];
     uint32_t total;
     {
         const uint32_t seg = (nviews + kSetupBlock - 1) / kSetupBlock;
@@ -280,12 +284,37 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
         }
         __syncthreads();
     }
-    const uint32_t lane = lane_id();
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     const unsigned long long lt = lanemask_lt();
+    // each wave takes a contiguous range of items (mostly of one view)
     const uint32_t wave0 = (blockIdx.x * kSetupBlock + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * kSetupBlock) >> 6;
+    const uint32_t per = (total + nwaves - 1) / nwaves;
+    const uint32_t i0 = min(total, wave0 * per), i1 = min(total, i0 + per);
+    uint32_t *const wkey = bkey[w];
+    uint2 *const wbox = bbox[w];
+    uint32_t nbuf = 0, bview = 0;
+    unsigned long long barea = 0;   // bbox pixels of the buffered survivors (lane 0)
     bool rerr = false;
-    for (uint32_t item = wave0; item < total; item += nwaves) {
+    // copy the wave's buffered survivors of view bview out with one atomic
+    auto flush = [&]() {
+        if (!nbuf) return;
+        uint32_t base = 0;
+        if (lane == 0) {
+            base = atomicAdd(&ctr[bview].surv_count, nbuf);
+            if (barea) atomicAdd(&ctr[bview].bbox_tests, barea);
+        }
+        base = __shfl(base, 0) + views[bview].surv_base;
+        __threadfence_block();
+        for (uint32_t i = lane; i < nbuf; i += 64) {
+            skey[base + i] = wkey[i];
+            sbox[base + i] = wbox[i];
+        }
+        __threadfence_block();
+        nbuf = 0;
+        barea = 0;
+    };
+    for (uint32_t item = i0; item < i1; ++item) {
         uint32_t lo = 0, hi = nviews - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
@@ -293,6 +322,10 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
             else hi = mid - 1;
         }
         const uint32_t vi = lo;
+        if (vi != bview) {
+            flush();
+            bview = vi;
+        }
         const DView &v = views[vi];
         const uint32_t first = (item - pre[vi]) * kRun;
         const uint32_t nrun = min(kRun, ctr[vi].vis_clusters - first);
@@ -319,7 +352,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
 #pragma unroll
         for (uint32_t j = 0; j < kRun; ++j)
             survive(v, P[j], valid[j], s[j][0], s[j][1], bx[j][0], bx[j][1], rerr);
-        // slots in (cluster, sub, lane) order
+        // buffer slots in (cluster, sub, lane) order
         uint32_t cnt = 0, mine[kRun][2];
 #pragma unroll
         for (uint32_t j = 0; j < kRun; ++j)
@@ -330,8 +363,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
                 cnt += (uint32_t)__popcll(m);
             }
         if (!cnt) continue;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&ctr[vi].surv_count, cnt);
+        if (nbuf + cnt > kSetupBuf) flush();   // cnt <= 2 kRun 64 = kSetupBuf
         if (v.count_work) {
             uint32_t area = 0;
 #pragma unroll
@@ -344,18 +376,19 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
             // of the wave sum cannot overflow
             const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
             const uint32_t ahi = wave_sum_u32(area >> 16);
-            if (lane == 0) atomicAdd(&ctr[vi].bbox_tests, (unsigned long long)alo + ((unsigned long long)ahi << 16));
+            barea += (unsigned long long)alo + ((unsigned long long)ahi << 16);
         }
-        base = __shfl(base, 0) + v.surv_base;
 #pragma unroll
         for (uint32_t j = 0; j < kRun; ++j)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
                 if (s[j][q]) {
-                    skey[base + mine[j][q]] = 2u * t[j] + (uint32_t)q;
-                    sbox[base + mine[j][q]] = pack_box(bx[j][q]);
+                    wkey[nbuf + mine[j][q]] = 2u * t[j] + (uint32_t)q;
+                    wbox[nbuf + mine[j][q]] = pack_box(bx[j][q]);
                 }
+        nbuf += cnt;
     }
+    flush();
     if (rerr) atomicOr(err, kErrRange);
 }
 
