@@ -39,6 +39,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` as rocprofv3's FETCH_SIZE/WRITE_SIZE
+    counted them (scaled by a plain-copy calibration), recorded by
+    paper_1904_01201_amd.rocprof_summary; None if the record is for another
+    kernel or the kernel sources changed since it was taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_01201_amd", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        from paper_1904_01201_amd.rocprof_summary import source_hash
+    except (OSError, ValueError, ImportError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_sha256") != source_hash():
+        return None
+    return t
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -238,9 +255,13 @@ def main():
     if dom == "raster":
         ops = OPS_PER_TEST * bbox_tests + OPS_PER_COVERED * covered
         ach = ops / (per_launch[dom] * 1e-3) / 1e12
-        roof = {"kernel": "+".join(f"k_raster<{k[6:]}>" for k in raster), "bound": "alu", "achieved": round(ach, 4),
+        kern = "+".join(f"k_raster<{k[6:]}>" for k in raster)
+        tr = measured_traffic(kern)
+        roof = {"kernel": kern, "bound": "alu", "achieved": round(ach, 4),
                 "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(ach / ALU_PEAK_TOPS, 5),
-                "traffic": None, "avg_launch_ms": round(per_launch[dom], 5),
+                "traffic": round(tr["bytes_per_launch"]) if tr else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "avg_launch_ms": round(per_launch[dom], 5),
                 "work_per_launch": {"bbox_tests": bbox_tests, "covered": covered,
                                     "ops": ops}}
     else:
@@ -350,16 +371,32 @@ def serve(a):
     sensors = [ctx.sensor(s.width, s.height, s.hfov_deg, s.near_m, s.outputs) for s in w.env_sensor]
     agents = loadgen.Agents(ctx, hs, w.env_scene, sensors, w.poses)
     srv = P.Server(ctx, num_streams=3, max_batch=256)
+    # closed loop at 1, 2, 4, ... agents (each keeps one request in flight)
+    agents_curve = []
+    na = 1
+    while na <= w.num_envs:
+        thr, lat_c = loadgen.saturate(srv, agents, seconds=min(a.serve_seconds, 0.5), num=na)
+        agents_curve.append({"agents": na, "throughput_rps": round(thr, 1),
+                             "p50_ms": round(float(np.percentile(lat_c, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat_c, 99)), 3), "requests": int(lat_c.size)})
+        log(f"closed loop, {na} agents: {agents_curve[-1]}")
+        na *= 2
     sat, lat_sat = loadgen.saturate(srv, agents, seconds=a.serve_seconds)
-    log(f"closed-loop saturation: {sat:.0f} requests/s, p50 {np.percentile(lat_sat, 50):.2f} ms")
+    log(f"closed-loop saturation ({w.num_envs} agents): {sat:.0f} requests/s, "
+        f"p50 {np.percentile(lat_sat, 50):.2f} ms")
+    # open loop: Poisson arrivals from 10% to 120% of saturation, at least
+    # 10k requests per point
     curve = []
     for frac in (0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.2):
-        thr, lat, bs = loadgen.open_loop(srv, agents, rate=frac * sat, seconds=a.serve_seconds,
-                                         seed=int(frac * 100))
-        pt = {"offered_frac": frac, "offered_rps": round(frac * sat, 1), "throughput_rps": round(thr, 1),
-              "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
-              "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
-              "mean_batch": round(float(bs.mean()), 1) if bs.size else None, "requests": int(lat.size)}
+        rate = frac * sat
+        secs = min(10.0, max(a.serve_seconds, 10_000 / rate))
+        thr, lat, e2e, bs = loadgen.open_loop(srv, agents, rate=rate, seconds=secs, seed=int(frac * 100))
+        pct = lambda x, q: round(float(np.percentile(x, q)), 3) if x.size else None
+        pt = {"offered_frac": frac, "offered_rps": round(rate, 1), "throughput_rps": round(thr, 1),
+              "p50_ms": pct(e2e, 50), "p99_ms": pct(e2e, 99),
+              "server_p50_ms": pct(lat, 50), "server_p99_ms": pct(lat, 99),
+              "mean_batch": round(float(bs.mean()), 1) if bs.size else None, "requests": int(lat.size),
+              "seconds": round(secs, 2)}
         curve.append(pt)
         log(f"offered {frac:.1f}x: {pt}")
     st = srv.stats()
@@ -374,7 +411,8 @@ def serve(a):
                                  "resident_bytes": int(resident), "agents": w.num_envs,
                                  "mean_pixels_per_request": round(float(np.mean(px)), 1),
                                  "streams": 3, "max_batch": 256},
-                      "curve": curve, "server_stats": st}), flush=True)
+                      "latency": "p50/p99 arrival -> completion; server_* submit -> completion",
+                      "agents_curve": agents_curve, "curve": curve, "server_stats": st}), flush=True)
 
 
 if __name__ == "__main__":

@@ -4,10 +4,12 @@ Agents submit single-view step requests (fixed scene and sensor per agent,
 poses from the agent's own random walk).  Arrivals are Poisson at a total
 rate lambda split evenly over the agents; an agent has at most one request
 in flight, so an arrival that falls while its previous request is still
-being served waits for that completion.  Latency is the server's own
-submit -> completion stamp.  `saturate()` measures the closed-loop
-throughput (every agent resubmits on completion) that the sweep is scaled
-by.
+being served waits for that completion.  Two latencies are kept: the
+server's own submit -> completion stamp, and arrival -> completion (which
+adds the wait for the agent's previous request).  `saturate()` measures
+the closed-loop throughput (every agent of the first `num` resubmits on
+completion) that the open-loop sweep is scaled by.  Arrival times are
+CLOCK_MONOTONIC, the clock of the server's stamps.
 """
 from __future__ import annotations
 
@@ -66,11 +68,12 @@ def _drain(srv, inflight, done_cb, limit=64):
     return finished
 
 
-def saturate(srv, agents: Agents, seconds=1.0):
-    """Closed loop: every agent keeps one request in flight."""
+def saturate(srv, agents: Agents, seconds=1.0, num=None):
+    """Closed loop: each of the first `num` agents keeps one request in
+    flight.  Returns requests/s and submit -> completion latencies (ms)."""
     inflight = {}
     lat = []
-    for a in range(agents.n):
+    for a in range(agents.n if num is None else min(num, agents.n)):
         inflight[agents.submit(srv, a)] = a
     t0 = time.perf_counter()
     done = 0
@@ -89,48 +92,56 @@ def saturate(srv, agents: Agents, seconds=1.0):
 
 
 def open_loop(srv, agents: Agents, rate, seconds=1.0, seed=0):
-    """Poisson arrivals at `rate` requests/s in total; returns throughput
-    and latency samples (ms)."""
+    """Poisson arrivals at `rate` requests/s in total over `seconds`.
+    Returns the throughput (requests completed inside the window per
+    second), submit -> completion and arrival -> completion latencies (ms)
+    of every request that arrived inside the window (those still waiting
+    when it ends are served and counted), and the batch size each request
+    rode in."""
     rng = np.random.default_rng(seed)
     per = rate / agents.n
     heap = [(float(rng.exponential(1.0 / per)), a) for a in range(agents.n)]
     heapq.heapify(heap)
     busy = np.zeros(agents.n, bool)
-    waiting = []                  # agents whose arrival came while busy
+    waiting = []                  # (agent, arrival) that came while the agent was busy
     inflight = {}
-    lat, bsz = [], []
-    t0 = time.perf_counter()
+    lat, e2e, bsz = [], [], []
+    t0 = time.monotonic()
+    t0_ns = int(t0 * 1e9)
+    end_ns = t0_ns + int(seconds * 1e9)
     done = 0
 
-    def cb(a, s_ns, d_ns, bs):
+    def cb(item, s_ns, d_ns, bs):
         nonlocal done
-        done += 1
+        a, ta = item
+        done += d_ns <= end_ns
         lat.append((d_ns - s_ns) * 1e-6)
+        e2e.append((d_ns - t0_ns) * 1e-6 - ta * 1e3)
         bsz.append(bs)
         busy[a] = False
 
     while True:
-        now = time.perf_counter() - t0
-        if now >= seconds and not inflight:
+        now = time.monotonic() - t0
+        if now >= seconds and not inflight and not waiting:
             break
         while heap and heap[0][0] <= now and now < seconds:
             ta, a = heapq.heappop(heap)
             if busy[a]:
-                waiting.append(a)
+                waiting.append((a, ta))
             else:
-                inflight[agents.submit(srv, a)] = a
+                inflight[agents.submit(srv, a)] = (a, ta)
                 busy[a] = True
             heapq.heappush(heap, (ta + float(rng.exponential(1.0 / per)), a))
         if inflight:
             _drain(srv, inflight, cb)
-        if waiting and now < seconds:
+        if waiting:
+            # every arrival inside the window is served, also after it ends
             still = []
-            for a in waiting:
+            for a, ta in waiting:
                 if busy[a]:
-                    still.append(a)
+                    still.append((a, ta))
                 else:
-                    inflight[agents.submit(srv, a)] = a
+                    inflight[agents.submit(srv, a)] = (a, ta)
                     busy[a] = True
             waiting = still
-    el = time.perf_counter() - t0
-    return done / el, np.array(lat), np.array(bsz)
+    return done / seconds, np.array(lat), np.array(e2e), np.array(bsz)
