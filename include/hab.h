@@ -260,10 +260,14 @@ hab_status hab_profile_enable(hab_context *ctx, int on);
 hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out);
 
 /* ---------------------------------------------------------- autotune */
-/* Time the candidate tile sizes and bin capacities on a sample batch and
- * remember the fastest for this batch class (scene size, resolution,
- * output mix); later calls with opts->tile_size == 0 use it.  Results are
- * identical for every choice. */
+/* Pick a tile size (8, 16, 32) and bin capacity factor (1, 2, 4) for every
+ * batch class (scene-size bucket, resolution bucket, output mix) of a
+ * sample batch by timing the whole batch: every choice for all classes,
+ * then other tile sizes class by class.  The context remembers the choices;
+ * later calls with opts->tile_size == 0 (and the stepper and server) use
+ * them.  *chosen_tile_size / *chosen_bin_factor (may be NULL) receive the
+ * first view's class's choice.  Renders on `stream` and synchronises it.
+ * Results are identical for every choice. */
 hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint32_t num_views,
                         hipStream_t stream, uint32_t *chosen_tile_size, float *chosen_bin_factor);
 

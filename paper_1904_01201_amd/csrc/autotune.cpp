@@ -1,8 +1,11 @@
-// Autotuner: for each batch class (scene-size bucket, resolution bucket,
-// output mix) present in a sample batch, time every tile size in {8, 16,
-// 32} and bin capacity factor in {1, 2, 4} on that class's views, and keep
-// the fastest in the context's table.  The choice cannot change any output
-// (the rendering definition does not depend on tiling or capacity).
+// Autotuner: picks a tile size in {8, 16, 32} and a bin capacity factor in
+// {1, 2, 4} for every batch class (scene-size bucket, resolution bucket,
+// output mix) of a sample batch, by timing the whole batch: first every
+// choice applied to all classes, then, class by class, the other tile
+// sizes for that class alone, kept when the whole batch gets faster by
+// more than 2%.  A candidate's time is the fastest of kReps renders.  The
+// choice cannot change any output (the rendering definition does not
+// depend on tiling or capacity).
 #include <algorithm>
 #include <map>
 #include <new>
@@ -11,6 +14,54 @@
 #include "runtime.h"
 
 using namespace habmi;
+
+namespace {
+
+constexpr int kReps = 5;
+constexpr float kKeepGain = 0.98f;   // a per-class change must beat the best by 2%
+
+struct Timer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Timer()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+void set_table(hab_context *ctx, const std::map<uint32_t, Tuned> &choice)
+{
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    for (const auto &kv : choice) {
+        auto it = std::find_if(ctx->tuned.begin(), ctx->tuned.end(),
+                               [&](const Tuned &t) { return t.key == kv.first; });
+        if (it != ctx->tuned.end()) *it = kv.second;
+        else ctx->tuned.push_back(kv.second);
+    }
+}
+
+// Fastest of kReps renders of the batch with the table's current choices.
+hab_status time_batch(hab_context *ctx, std::vector<ViewReq> &req, hipStream_t s, Timer &t, float *ms)
+{
+    PlanOpts o;   // tile size 0: every class takes its table entry
+    hab_status rc = render_all(ctx, ctx->ws, req.data(), (uint32_t)req.size(), o, s, nullptr);
+    if (rc != HAB_OK) return rc;
+    float best = 1e30f;
+    for (int r = 0; r < kReps; ++r) {
+        if (hipEventRecord(t.e0, s) != hipSuccess) return HAB_ERR_DEVICE;
+        rc = render_all(ctx, ctx->ws, req.data(), (uint32_t)req.size(), o, s, nullptr);
+        if (rc != HAB_OK) return rc;
+        float e = 0.0f;
+        if (hipEventRecord(t.e1, s) != hipSuccess || hipEventSynchronize(t.e1) != hipSuccess ||
+            hipEventElapsedTime(&e, t.e0, t.e1) != hipSuccess)
+            return HAB_ERR_DEVICE;
+        best = std::min(best, e);
+    }
+    *ms = best;
+    return HAB_OK;
+}
+
+}  // namespace
 
 extern "C" hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint32_t n,
                                    hipStream_t stream, uint32_t *chosen_ts, float *chosen_bf)
@@ -22,60 +73,61 @@ extern "C" hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint
             hab_status s = to_view_req(views[k], req[k]);
             if (s != HAB_OK) return s;
         }
-        std::map<uint32_t, std::vector<ViewReq>> classes;
-        for (const ViewReq &r : req) classes[class_key(r.scene, &r.sensor)].push_back(r);
+        std::map<uint32_t, Tuned> choice;
+        for (const ViewReq &r : req) {
+            const uint32_t key = class_key(r.scene, &r.sensor);
+            choice[key] = Tuned{key, 16, 2.0f};
+        }
         int prev = -1;
         (void)hipGetDevice(&prev);
         if (hipSetDevice(ctx->device) != hipSuccess) return HAB_ERR_DEVICE;
-        hipEvent_t e0, e1;
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HAB_ERR_DEVICE;
-        const uint32_t first_key = class_key(req[0].scene, &req[0].sensor);
+        Timer t;
+        if (hipEventCreate(&t.e0) != hipSuccess || hipEventCreate(&t.e1) != hipSuccess) return HAB_ERR_DEVICE;
         hab_status rc = HAB_OK;
-        for (auto &kv : classes) {
-            float best_ms = 1e30f;
-            Tuned best{kv.first, 16, 2.0f};
-            for (uint32_t ts : {8u, 16u, 32u}) {
-                for (float bf : {1.0f, 2.0f, 4.0f}) {
-                    PlanOpts o;
-                    o.tile_size = ts;
-                    o.bin_factor = bf;
-                    std::vector<ViewReq> &v = kv.second;
-                    rc = render_all(ctx, ctx->ws, v.data(), (uint32_t)v.size(), o, stream, nullptr);
-                    if (rc != HAB_OK) break;
-                    float tot = 0.0f;
-                    const int reps = 3;
-                    if (hipEventRecord(e0, stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
-                    for (int r = 0; r < reps && rc == HAB_OK; ++r)
-                        rc = render_all(ctx, ctx->ws, v.data(), (uint32_t)v.size(), o, stream, nullptr);
-                    if (rc != HAB_OK) break;
-                    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                        rc = HAB_ERR_DEVICE;
-                        break;
-                    }
-                    if (hipEventElapsedTime(&tot, e0, e1) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
-                    if (tot < best_ms) {
-                        best_ms = tot;
-                        best.ts = ts;
-                        best.bin_factor = bf;
-                    }
-                }
+        float best_ms = 1e30f;
+        std::map<uint32_t, Tuned> best = choice;
+        // 1. one choice for every class
+        for (uint32_t ts : {8u, 16u, 32u}) {
+            for (float bf : {1.0f, 2.0f, 4.0f}) {
+                for (auto &kv : choice) kv.second = Tuned{kv.first, ts, bf};
+                set_table(ctx, choice);
+                float ms = 0.0f;
+                rc = time_batch(ctx, req, stream, t, &ms);
                 if (rc != HAB_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = choice;
+                }
             }
             if (rc != HAB_OK) break;
-            {
-                std::lock_guard<std::mutex> g(ctx->tune_mu);
-                auto it = std::find_if(ctx->tuned.begin(), ctx->tuned.end(),
-                                       [&](const Tuned &t) { return t.key == best.key; });
-                if (it != ctx->tuned.end()) *it = best;
-                else ctx->tuned.push_back(best);
-            }
-            if (kv.first == first_key) {
-                if (chosen_ts) *chosen_ts = best.ts;
-                if (chosen_bf) *chosen_bf = best.bin_factor;
+        }
+        // 2. class by class, another tile size for that class alone
+        if (rc == HAB_OK && best.size() > 1) {
+            for (auto &kv : best) {
+                const Tuned keep = kv.second;
+                Tuned won = keep;
+                for (uint32_t ts : {8u, 16u, 32u}) {
+                    if (ts == keep.ts) continue;
+                    kv.second.ts = ts;
+                    set_table(ctx, best);
+                    float ms = 0.0f;
+                    rc = time_batch(ctx, req, stream, t, &ms);
+                    if (rc != HAB_OK) break;
+                    if (ms < best_ms * kKeepGain) {
+                        best_ms = ms;
+                        won = kv.second;
+                    }
+                }
+                kv.second = won;
+                if (rc != HAB_OK) break;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        set_table(ctx, best);
+        if (rc == HAB_OK) {
+            const Tuned &first = best[class_key(req[0].scene, &req[0].sensor)];
+            if (chosen_ts) *chosen_ts = first.ts;
+            if (chosen_bf) *chosen_bf = first.bin_factor;
+        }
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;
     } catch (const std::bad_alloc &) {

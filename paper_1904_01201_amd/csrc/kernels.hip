@@ -829,9 +829,11 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     __shared__ LRec srec[NT];
     __shared__ LExt sext[NT];
     __shared__ QM sqm[NT];
+    __shared__ uint8_t slist[NT / 64][4][64];   // per wave and quarter: chunk-relative record indices
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const unsigned long long lt = lanemask_lt();
     const int sx = (int)(wave % NS), sy = (int)(wave / NS);
     const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
     const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
@@ -970,22 +972,37 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             // own lists of records whose box touches them: one step tests up
             // to four records.  Bits qb, qb+1, qb+NQ, qb+NQ+1 of a record's
             // quarter mask are this wave's quarters.
+            // Per chunk of 64 records, each quarter's relevant records are
+            // compacted into its LDS list; step i then tests entry i of every
+            // quarter's list.
             const uint32_t qb = (uint32_t)(2 * sy * NQ + 2 * sx);
             const uint32_t lq = ((lane >> 5) << 1) | ((lane >> 2) & 1u);
+            uint8_t *const wl = &slist[wave][0][0];
             for (uint32_t g = 0; g < m; g += 64) {
                 const QM qm = (g + lane < m) ? sqm[g + lane] : (QM)0;
-                const unsigned long long m0 = __ballot((qm >> qb) & 1u);
-                const unsigned long long m1 = __ballot((qm >> (qb + 1)) & 1u);
-                const unsigned long long m2 = __ballot((qm >> (qb + NQ)) & 1u);
-                const unsigned long long m3 = __ballot((qm >> (qb + NQ + 1)) & 1u);
+                const bool r0 = (qm >> qb) & 1u, r1 = (qm >> (qb + 1)) & 1u;
+                const bool r2 = (qm >> (qb + NQ)) & 1u, r3 = (qm >> (qb + NQ + 1)) & 1u;
+                const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
+                const unsigned long long m2 = __ballot(r2), m3 = __ballot(r3);
                 if (!(m0 | m1 | m2 | m3)) continue;
-                unsigned long long mine = lq == 0 ? m0 : lq == 1 ? m1 : lq == 2 ? m2 : m3;
-                while (__ballot(mine != 0ull)) {
-                    const bool act = mine != 0ull;
-                    const uint32_t k = g + (act ? (uint32_t)(__ffsll((long long)mine) - 1) : 0u);
-                    mine &= mine - 1ull;
+                if (r0) wl[0 * 64 + __popcll(m0 & lt)] = (uint8_t)lane;
+                if (r1) wl[1 * 64 + __popcll(m1 & lt)] = (uint8_t)lane;
+                if (r2) wl[2 * 64 + __popcll(m2 & lt)] = (uint8_t)lane;
+                if (r3) wl[3 * 64 + __popcll(m3 & lt)] = (uint8_t)lane;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
+                const uint32_t c2 = (uint32_t)__popcll(m2), c3 = (uint32_t)__popcll(m3);
+                const uint32_t nsteps = max(max(c0, c1), max(c2, c3));
+                const uint32_t myc = lq == 0 ? c0 : lq == 1 ? c1 : lq == 2 ? c2 : c3;
+                const uint8_t *const myl = wl + lq * 64;
+                for (uint32_t i = 0; i < nsteps; ++i) {
+                    const bool act = i < myc;
+                    // entries past a list's count are stale: masked into the
+                    // chunk, and unused
+                    const uint32_t k = g + ((uint32_t)myl[i] & 63u);
                     visit(lds_rec(srec, k), k, act);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
             __syncthreads();
         }
