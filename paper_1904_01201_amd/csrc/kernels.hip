@@ -43,6 +43,10 @@ namespace habmi {
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// A value every lane of the wave holds alike, moved to a scalar register so
+// that what it indexes is fetched through the scalar cache.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
 __device__ __forceinline__ unsigned long long lanemask_lt()
 {
     return (1ull << lane_id()) - 1ull;
@@ -108,15 +112,28 @@ __device__ __forceinline__ uint2 pack_box(const PixBox &b)
     return make_uint2((uint32_t)b.i0 | ((uint32_t)b.j0 << 16), (uint32_t)b.i1 | ((uint32_t)b.j1 << 16));
 }
 
+// A pointer read out of a view record, known to point into device global
+// memory: loads through it are global (vector memory only), not flat.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gmem(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem_out(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 __device__ __forceinline__ void load_tri(const DView &v, uint32_t t, float P[9], uint32_t vid[3])
 {
-    const uint32_t *ix = v.idx + 3ull * t;
+    const auto *ix = gmem(v.idx) + 3ull * t;
     vid[0] = ix[0];
     vid[1] = ix[1];
     vid[2] = ix[2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float *p = v.pos + 3ull * vid[k];
+        const auto *p = gmem(v.pos) + 3ull * vid[k];
         P[3 * k + 0] = p[0];
         P[3 * k + 1] = p[1];
         P[3 * k + 2] = p[2];
@@ -240,7 +257,11 @@ __global__ __launch_bounds__(kScanBlock) void k_cull(const DView *__restrict__ v
     uint32_t run = 0;
     for (uint32_t base = 0; base < ncl; base += kScanBlock) {
         const uint32_t c = base + threadIdx.x;
-        const bool vis = c < ncl && !(v.cbox && box_outside(v, v.cbox[2 * c], v.cbox[2 * c + 1]));
+        bool vis = c < ncl;
+        if (vis && v.cbox) {
+            const auto *b = gmem(reinterpret_cast<const float *>(v.cbox)) + 8ull * c;
+            vis = !box_outside(v, make_float4(b[0], b[1], b[2], b[3]), make_float4(b[4], b[5], b[6], b[7]));
+        }
         uint32_t tot;
         const uint32_t ex = block_excl_scan<kScanBlock>(vis ? 1u : 0u, wtot, &tot);
         if (vis) vis_clusters[v.pair_base + run + ex] = c;
@@ -287,7 +308,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     const unsigned long long lt = lanemask_lt();
     // each wave takes a contiguous range of items (mostly of one view)
-    const uint32_t wave0 = (blockIdx.x * kSetupBlock + threadIdx.x) >> 6;
+    const uint32_t wave0 = uniform((blockIdx.x * kSetupBlock + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * kSetupBlock) >> 6;
     const uint32_t per = (total + nwaves - 1) / nwaves;
     const uint32_t i0 = min(total, wave0 * per), i1 = min(total, i0 + per);
@@ -321,7 +342,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
             if (pre[mid] <= item) lo = mid;
             else hi = mid - 1;
         }
-        const uint32_t vi = lo;
+        const uint32_t vi = uniform(lo);
         if (vi != bview) {
             flush();
             bview = vi;
@@ -459,7 +480,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
     const uint32_t total = build_item_prefix(ctr, nviews, pre, wtot);
     const uint32_t tid = threadIdx.x;
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const uint32_t vi = find_view(pre, nviews, item);
+        const uint32_t vi = uniform(find_view(pre, nviews, item));
         const DView &v = views[vi];
         const uint32_t cnt = ctr[vi].surv_count;
         const uint32_t s0 = (item - pre[vi]) * kBinChunk;
@@ -767,9 +788,9 @@ __device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int
     cam_xform(v, P[0], P[1], P[2], c0);
     cam_xform(v, P[3], P[4], P[5], c1);
     cam_xform(v, P[6], P[7], P[8], c2);
-    const uint32_t k0 = v.col ? v.col[vid[0]] : 0xFFFFFFu;
-    const uint32_t k1 = v.col ? v.col[vid[1]] : 0xFFFFFFu;
-    const uint32_t k2 = v.col ? v.col[vid[2]] : 0xFFFFFFu;
+    const uint32_t k0 = v.col ? gmem(v.col)[vid[0]] : 0xFFFFFFu;
+    const uint32_t k1 = v.col ? gmem(v.col)[vid[1]] : 0xFFFFFFu;
+    const uint32_t k2 = v.col ? gmem(v.col)[vid[2]] : 0xFFFFFFu;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         c0.a[ch] = (float)unpack_rgb(k0, ch);
@@ -852,7 +873,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             s_item = ((k / kQueueGroup) * nq + x) * kQueueGroup + k % kQueueGroup;
         }
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = uniform(s_item);
         __syncthreads();
         if (item >= total) break;
         const uint2 it = items[item];
@@ -1033,7 +1054,7 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
         if (lpre[mid] <= blk) lo = mid;
         else hi = mid - 1;
     }
-    const uint32_t vi = lview[lo];
+    const uint32_t vi = uniform(lview[uniform(lo)]);
     const DView &v = views[vi];
     const uint32_t tile = blk - lpre[lo];
     const int tx = (int)(tile % v.tiles_x), ty = (int)(tile / v.tiles_x);
@@ -1059,12 +1080,13 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
     if (best_key != kNone && !resolve(v, best_key, pi, pj, rgb, depth)) atomicOr(err, kErrResolve);
     const size_t p = (size_t)pj * v.W + (size_t)pi;
     if (v.rgb) {
-        v.rgb[3 * p + 0] = (uint8_t)rgb[0];
-        v.rgb[3 * p + 1] = (uint8_t)rgb[1];
-        v.rgb[3 * p + 2] = (uint8_t)rgb[2];
+        auto *o = gmem_out(v.rgb) + 3 * p;
+        o[0] = (uint8_t)rgb[0];
+        o[1] = (uint8_t)rgb[1];
+        o[2] = (uint8_t)rgb[2];
     }
-    if (v.depth) v.depth[p] = depth;
-    if (v.tri) v.tri[p] = best_key == kNone ? kNone : (best_key >> 1);
+    if (v.depth) gmem_out(v.depth)[p] = depth;
+    if (v.tri) gmem_out(v.tri)[p] = best_key == kNone ? kNone : (best_key >> 1);
 }
 
 // ------------------------------------------------------------ host side
