@@ -448,8 +448,9 @@ __device__ __forceinline__ uint32_t find_view(const uint32_t *pre, uint32_t nvie
     return lo;
 }
 
+// Tiles [tx0, tx1] x [ty0, ty1] that a survivor's pixel box touches.
 struct TileRange {
-    int tx0, ty0, nx, n;
+    int tx0, ty0, tx1, ty1;
 };
 
 __device__ __forceinline__ TileRange tile_range(uint2 bb, uint32_t ts)
@@ -457,9 +458,8 @@ __device__ __forceinline__ TileRange tile_range(uint2 bb, uint32_t ts)
     TileRange r;
     r.tx0 = (int)(bb.x & 0xFFFFu) >> ts;
     r.ty0 = (int)(bb.x >> 16) >> ts;
-    const int tx1 = (int)(bb.y & 0xFFFFu) >> ts, ty1 = (int)(bb.y >> 16) >> ts;
-    r.nx = tx1 - r.tx0 + 1;
-    r.n = r.nx * (ty1 - r.ty0 + 1);
+    r.tx1 = (int)(bb.y & 0xFFFFu) >> ts;
+    r.ty1 = (int)(bb.y >> 16) >> ts;
     return r;
 }
 
@@ -496,8 +496,8 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                 const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
                 if (s >= cnt) break;
                 const TileRange R = tile_range(sbox[v.surv_base + s], ts);
-                for (int k = 0; k < R.n; ++k)
-                    atomicAdd(&hist[(uint32_t)(R.ty0 + k / R.nx) * v.tiles_x + (uint32_t)(R.tx0 + k % R.nx)], 1u);
+                for (int ty = R.ty0; ty <= R.ty1; ++ty)
+                    for (int tx = R.tx0; tx <= R.tx1; ++tx) atomicAdd(&hist[(uint32_t)ty * v.tiles_x + (uint32_t)tx], 1u);
             }
             __syncthreads();
             // one global operation per touched tile
@@ -519,13 +519,14 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                     if (s >= cnt) break;
                     const TileRange R = tile_range(sbox[v.surv_base + s], ts);
                     const uint32_t key = skey[v.surv_base + s];
-                    for (int k = 0; k < R.n; ++k) {
-                        const uint32_t tl = (uint32_t)(R.ty0 + k / R.nx) * v.tiles_x + (uint32_t)(R.tx0 + k % R.nx);
-                        const uint32_t b = lbase[tl];
-                        if (b == kOverflow) continue;
-                        const uint32_t rank = atomicAdd(&hist[tl], 1u << 16) >> 16;
-                        bins[v.bin_base + b + rank] = key;
-                    }
+                    for (int ty = R.ty0; ty <= R.ty1; ++ty)
+                        for (int tx = R.tx0; tx <= R.tx1; ++tx) {
+                            const uint32_t tl = (uint32_t)ty * v.tiles_x + (uint32_t)tx;
+                            const uint32_t b = lbase[tl];
+                            if (b == kOverflow) continue;
+                            const uint32_t rank = atomicAdd(&hist[tl], 1u << 16) >> 16;
+                            bins[v.bin_base + b + rank] = key;
+                        }
                 }
             }
             __syncthreads();
@@ -535,23 +536,29 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
             for (int r = 0; r < kBinItems; ++r) {
                 const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
                 const bool has = s < cnt;
-                TileRange R = {0, 0, 1, 0};
+                TileRange R = {0, 0, -1, -1};   // empty
                 uint32_t key = 0;
                 if (has) {
                     R = tile_range(sbox[v.surv_base + s], ts);
                     if (SCATTER) key = skey[v.surv_base + s];
                 }
-                for (int k = 0; __ballot(k < R.n); ++k) {
-                    bool act = k < R.n;
+                // every lane walks its box's tiles row by row
+                int tx = R.tx0, ty = R.ty0;
+                while (__ballot(ty <= R.ty1)) {
+                    bool act = ty <= R.ty1;
                     uint32_t tile = 0;
-                    if (act) tile = v.tile_base + (uint32_t)(R.ty0 + k / R.nx) * v.tiles_x + (uint32_t)(R.tx0 + k % R.nx);
+                    if (act) tile = v.tile_base + (uint32_t)ty * v.tiles_x + (uint32_t)tx;
                     if (!SCATTER) {
                         wave_aggregated_add(tile_count, tile, act);
                     } else {
                         const uint32_t off = act ? tile_off[tile] : kOverflow;
-                        act = act && off != kOverflow;
-                        const uint32_t slot = wave_aggregated_add(tile_cursor, tile, act);
-                        if (act) bins[v.bin_base + off + slot] = key;
+                        const bool put = act && off != kOverflow;
+                        const uint32_t slot = wave_aggregated_add(tile_cursor, tile, put);
+                        if (put) bins[v.bin_base + off + slot] = key;
+                    }
+                    if (act && ++tx > R.tx1) {
+                        tx = R.tx0;
+                        ++ty;
                     }
                 }
             }
