@@ -13,6 +13,7 @@ CLOCK_MONOTONIC, the clock of the server's stamps.
 """
 from __future__ import annotations
 
+import collections
 import ctypes as C
 import heapq
 import time
@@ -103,7 +104,8 @@ def open_loop(srv, agents: Agents, rate, seconds=1.0, seed=0):
     heap = [(float(rng.exponential(1.0 / per)), a) for a in range(agents.n)]
     heapq.heapify(heap)
     busy = np.zeros(agents.n, bool)
-    waiting = []                  # (agent, arrival) that came while the agent was busy
+    backlog = [collections.deque() for _ in range(agents.n)]   # arrivals while busy
+    nback = 0
     inflight = {}
     lat, e2e, bsz = [], [], []
     t0 = time.monotonic()
@@ -112,36 +114,31 @@ def open_loop(srv, agents: Agents, rate, seconds=1.0, seed=0):
     done = 0
 
     def cb(item, s_ns, d_ns, bs):
-        nonlocal done
+        nonlocal done, nback
         a, ta = item
         done += d_ns <= end_ns
         lat.append((d_ns - s_ns) * 1e-6)
         e2e.append((d_ns - t0_ns) * 1e-6 - ta * 1e3)
         bsz.append(bs)
-        busy[a] = False
+        if backlog[a]:
+            nback -= 1
+            inflight[agents.submit(srv, a)] = (a, backlog[a].popleft())
+        else:
+            busy[a] = False
 
     while True:
         now = time.monotonic() - t0
-        if now >= seconds and not inflight and not waiting:
+        if now >= seconds and not inflight and not nback:
             break
         while heap and heap[0][0] <= now and now < seconds:
             ta, a = heapq.heappop(heap)
             if busy[a]:
-                waiting.append((a, ta))
+                backlog[a].append(ta)
+                nback += 1
             else:
                 inflight[agents.submit(srv, a)] = (a, ta)
                 busy[a] = True
             heapq.heappush(heap, (ta + float(rng.exponential(1.0 / per)), a))
         if inflight:
             _drain(srv, inflight, cb)
-        if waiting:
-            # every arrival inside the window is served, also after it ends
-            still = []
-            for a, ta in waiting:
-                if busy[a]:
-                    still.append((a, ta))
-                else:
-                    inflight[agents.submit(srv, a)] = (a, ta)
-                    busy[a] = True
-            waiting = still
     return done / seconds, np.array(lat), np.array(e2e), np.array(bsz)
