@@ -660,10 +660,10 @@ struct alignas(16) LExt {
 };
 static_assert(sizeof(LRec) == 48 && sizeof(LExt) == 32, "LDS records");
 
-// One record as three 16-byte LDS loads.
-__device__ __forceinline__ LRec lds_rec(const LRec *base, uint32_t k)
+// One record as three 16-byte LDS loads, at a byte offset from the array.
+__device__ __forceinline__ LRec lds_rec_at(const char *base, uint32_t off)
 {
-    const uint4 *p = reinterpret_cast<const uint4 *>(base + k);
+    const uint4 *p = reinterpret_cast<const uint4 *>(base + off);
     const uint4 a = p[0], b = p[1], c = p[2];
     LRec r;
     r.c0 = (int)a.x;
@@ -681,10 +681,11 @@ __device__ __forceinline__ LRec lds_rec(const LRec *base, uint32_t k)
     return r;
 }
 
-// flags: bits 16..18 edge k not owned, 19 slow (int64 edge values), 20
-// packed (every edge delta fits int16)
-constexpr uint32_t kSlow = 1u << 19;
-constexpr uint32_t kPacked = 1u << 20;
+// flags: byte k (k = 0, 1, 2) is 1 when edge k is not owned (the pixel needs
+// E_k > 0; a byte of its own lets a compare read it directly), bit 24 slow
+// (int64 edge values), bit 25 packed (every edge delta fits int16)
+constexpr uint32_t kSlow = 1u << 24;
+constexpr uint32_t kPacked = 1u << 25;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
@@ -735,7 +736,7 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         C[k] = (long long)dx[k] * (Oy - ay[k]) - (long long)dy[k] * (Ox - ax[k]);
-        if (!owned(dx[k], dy[k])) notown |= 1u << k;
+        if (!owned(dx[k], dy[k])) notown |= 1u << (8 * k);
         const long long qx = (long long)dx[k] * PM, px = -(long long)dy[k] * PM;
         const long long emax = C[k] + (qx > 0 ? qx : 0) + (px > 0 ? px : 0);
         const long long emin = C[k] + (qx < 0 ? qx : 0) + (px < 0 ? px : 0);
@@ -771,7 +772,7 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     r.rw1 = b.rw;
     r.rw2 = c.rw;
     r.nkey = ~key;
-    r.flags = (notown << 16) | (fast ? 0u : kSlow) | (packed ? kPacked : 0u);
+    r.flags = notown | (fast ? 0u : kSlow) | (packed ? kPacked : 0u);
     return true;
 }
 
@@ -857,11 +858,14 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     __shared__ LRec srec[NT];
     __shared__ LExt sext[NT];
     __shared__ QM sqm[NT];
-    __shared__ uint8_t slist[NT / 64][4][64];   // per wave and quarter: chunk-relative record indices
+    // per wave and quarter: byte offsets in srec of the chunk's records that
+    // touch the quarter (zeroed once, so a stale entry is still a record)
+    __shared__ uint16_t slist[NT / 64][4][64];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const unsigned long long lt = lanemask_lt();
+    for (uint32_t i = lane; i < 4 * 64; i += 64) (&slist[wave][0][0])[i] = 0;
     const int sx = (int)(wave % NS), sy = (int)(wave / NS);
     const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
     const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
@@ -891,6 +895,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
         const int ti0 = tx * TS, tj0 = ty * TS;
         const bool inview = ti0 + sx * 8 + li < (int)v.W && tj0 + sy * 8 + lj < (int)v.H;
         const unsigned long long inmask = __ballot(inview);
+        const bool count = v.count_work != 0;
 
         const uint32_t tglob = v.tile_base + tile;
         const uint32_t cnt = tile_count[tglob];
@@ -943,16 +948,16 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                 const float rho = num * R.invA;
                 const unsigned long long cand =
                     ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
-                ncov += (uint32_t)__popcll(cm & inmask);
+                if (count) ncov += (uint32_t)__popcll(cm & inmask);
                 best = (cov && cand > best) ? cand : best;
             };
             // one step: every active lane tests its pixel against record R
             // (index k) of its quarter under the top-left rule (an edge not
             // owned needs E > 0)
-            auto visit = [&](const LRec &R, uint32_t k, bool act) {
+            auto visit = [&](const LRec &R, uint32_t k, bool act, auto allpk) {
                 const uint32_t fl = R.flags;
-                const int n0 = (int)((fl >> 16) & 1u), n1 = (int)((fl >> 17) & 1u), n2 = (int)((fl >> 18) & 1u);
-                if (!__ballot(act && !(fl & kPacked))) {
+                const int n0 = (int)(fl & 0xFFu), n1 = (int)((fl >> 8) & 0xFFu), n2 = (int)((fl >> 16) & 0xFFu);
+                if (decltype(allpk)::value || !__ballot(act && !(fl & kPacked))) {
                     // every active lane's record is packed
                     const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
                     const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
@@ -1005,30 +1010,40 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             // quarter's list.
             const uint32_t qb = (uint32_t)(2 * sy * NQ + 2 * sx);
             const uint32_t lq = ((lane >> 5) << 1) | ((lane >> 2) & 1u);
-            uint8_t *const wl = &slist[wave][0][0];
+            uint16_t *const wl = &slist[wave][0][0];
             for (uint32_t g = 0; g < m; g += 64) {
-                const QM qm = (g + lane < m) ? sqm[g + lane] : (QM)0;
+                const bool in = g + lane < m;
+                const QM qm = in ? sqm[g + lane] : (QM)0;
                 const bool r0 = (qm >> qb) & 1u, r1 = (qm >> (qb + 1)) & 1u;
                 const bool r2 = (qm >> (qb + NQ)) & 1u, r3 = (qm >> (qb + NQ + 1)) & 1u;
                 const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
                 const unsigned long long m2 = __ballot(r2), m3 = __ballot(r3);
                 if (!(m0 | m1 | m2 | m3)) continue;
-                if (r0) wl[0 * 64 + __popcll(m0 & lt)] = (uint8_t)lane;
-                if (r1) wl[1 * 64 + __popcll(m1 & lt)] = (uint8_t)lane;
-                if (r2) wl[2 * 64 + __popcll(m2 & lt)] = (uint8_t)lane;
-                if (r3) wl[3 * 64 + __popcll(m3 & lt)] = (uint8_t)lane;
+                const uint16_t off = (uint16_t)((g + lane) * sizeof(LRec));
+                if (r0) wl[0 * 64 + __popcll(m0 & lt)] = off;
+                if (r1) wl[1 * 64 + __popcll(m1 & lt)] = off;
+                if (r2) wl[2 * 64 + __popcll(m2 & lt)] = off;
+                if (r3) wl[3 * 64 + __popcll(m3 & lt)] = off;
+                // does every record this wave will test have the packed form?
+                const bool rel = r0 || r1 || r2 || r3;
+                const bool allpk = !__ballot(rel && !(srec[g + lane].flags & kPacked));
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
                 const uint32_t c2 = (uint32_t)__popcll(m2), c3 = (uint32_t)__popcll(m3);
-                const uint32_t nsteps = max(max(c0, c1), max(c2, c3));
+                const uint32_t nsteps = uniform(max(max(c0, c1), max(c2, c3)));
                 const uint32_t myc = lq == 0 ? c0 : lq == 1 ? c1 : lq == 2 ? c2 : c3;
-                const uint8_t *const myl = wl + lq * 64;
-                for (uint32_t i = 0; i < nsteps; ++i) {
-                    const bool act = i < myc;
-                    // entries past a list's count are stale: masked into the
-                    // chunk, and unused
-                    const uint32_t k = g + ((uint32_t)myl[i] & 63u);
-                    visit(lds_rec(srec, k), k, act);
+                const uint16_t *const myl = wl + lq * 64;
+                const char *const rb = reinterpret_cast<const char *>(srec);
+                if (allpk) {
+                    for (uint32_t i = 0; i < nsteps; ++i) {
+                        const uint32_t o = myl[i];
+                        visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::true_type());
+                    }
+                } else {
+                    for (uint32_t i = 0; i < nsteps; ++i) {
+                        const uint32_t o = myl[i];
+                        visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::false_type());
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
