@@ -29,6 +29,7 @@ struct RasterLaunch {
 struct LaunchPlan {
     const DView *views;
     uint32_t nviews;
+    uint32_t cull_blocks;      // cull blocks per view (256 clusters each, for the largest scene)
     uint32_t setup_grid;       // setup grid (waves stride over the visible cluster runs)
     uint32_t *pairs;           // visible clusters, one segment per view
     DViewCounters *ctr;

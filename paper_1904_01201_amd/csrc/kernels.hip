@@ -243,31 +243,35 @@ __device__ __forceinline__ bool box_outside(const DView &v, float4 mn, float4 mx
     return r || l || u || d || n;
 }
 
-// One block per view: test every 64-triangle cluster of the view's scene
-// against the view's frustum and write the visible ones, in cluster order,
-// to the view's segment of the pair list (a block scan: no atomics).
-__global__ __launch_bounds__(kScanBlock) void k_cull(const DView *__restrict__ views,
+// Block (x, view): test kCullBlock consecutive 64-triangle clusters of the
+// view's scene against the view's frustum, compact the visible ones with a
+// block scan and append them to the view's segment of the visible-cluster
+// list behind one reservation (their order there is immaterial: nothing
+// downstream depends on it).
+constexpr int kCullBlock = 256;
+
+__global__ __launch_bounds__(kCullBlock) void k_cull(const DView *__restrict__ views,
                                                      DViewCounters *__restrict__ ctr,
                                                      uint32_t *__restrict__ vis_clusters)
 {
-    __shared__ uint32_t wtot[kScanBlock / 64];
-    const uint32_t vi = blockIdx.x;
+    __shared__ uint32_t wtot[kCullBlock / 64];
+    __shared__ uint32_t sbase;
+    const uint32_t vi = blockIdx.y;
     const DView &v = views[vi];
     const uint32_t ncl = (v.T + kCluster - 1) / kCluster;
-    uint32_t run = 0;
-    for (uint32_t base = 0; base < ncl; base += kScanBlock) {
-        const uint32_t c = base + threadIdx.x;
-        bool vis = c < ncl;
-        if (vis && v.cbox) {
-            const auto *b = gmem(reinterpret_cast<const float *>(v.cbox)) + 8ull * c;
-            vis = !box_outside(v, make_float4(b[0], b[1], b[2], b[3]), make_float4(b[4], b[5], b[6], b[7]));
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<kScanBlock>(vis ? 1u : 0u, wtot, &tot);
-        if (vis) vis_clusters[v.pair_base + run + ex] = c;
-        run += tot;
+    const uint32_t c0 = blockIdx.x * kCullBlock;
+    if (c0 >= ncl) return;
+    const uint32_t c = c0 + threadIdx.x;
+    bool vis = c < ncl;
+    if (vis && v.cbox) {
+        const auto *b = gmem(reinterpret_cast<const float *>(v.cbox)) + 8ull * c;
+        vis = !box_outside(v, make_float4(b[0], b[1], b[2], b[3]), make_float4(b[4], b[5], b[6], b[7]));
     }
-    if (threadIdx.x == 0) ctr[vi].vis_clusters = run;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<kCullBlock>(vis ? 1u : 0u, wtot, &tot);
+    if (threadIdx.x == 0) sbase = tot ? atomicAdd(&ctr[vi].vis_clusters, tot) : 0u;
+    __syncthreads();
+    if (vis) vis_clusters[v.pair_base + sbase + ex] = c;
 }
 
 // Work items of k_setup: (view, run of kRun visible clusters).  Each block
@@ -1155,7 +1159,7 @@ hipError_t launch_render(const LaunchPlan &L, hipStream_t s)
                        L.nviews, L.tile_count, L.tile_cursor, L.ntiles, L.queue);
     mark(L, 1, s);
     mark(L, 2, s);
-    hipLaunchKernelGGL(k_cull, dim3(L.nviews), dim3(kScanBlock), 0, s, L.views, L.ctr, L.pairs);
+    hipLaunchKernelGGL(k_cull, dim3(L.cull_blocks, L.nviews), dim3(kCullBlock), 0, s, L.views, L.ctr, L.pairs);
     hipLaunchKernelGGL(k_setup, dim3(L.setup_grid), dim3(kSetupBlock), 0, s, L.views, L.nviews, L.ctr,
                        L.pairs, L.skey, L.sbox, L.err);
     mark(L, 3, s);

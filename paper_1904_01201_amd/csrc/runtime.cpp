@@ -313,6 +313,9 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     LaunchPlan &L = plan.L;
     L = LaunchPlan{};
     L.nviews = n;
+    uint32_t max_t = 0;
+    for (uint32_t k = 0; k < n; ++k) max_t = std::max(max_t, dv[k].T);
+    L.cull_blocks = std::max<uint32_t>(1, cdiv(cdiv(max_t, kCluster), 256));
     L.setup_grid = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>((npairs + 15) / 16, 8ull * (ctx ? ctx->cu_count : 256)));
     L.ntiles = (uint32_t)tile_total;
