@@ -56,6 +56,78 @@ def measured_traffic(kernel: str):
     return t
 
 
+def other_workloads(ctx, a):
+    """Throughput of the plain path on the room and apartment-walk
+    workloads (one hab_render call per view, in order, one stream) and of
+    the mixed 256-environment batch through the captured stepper."""
+    import torch
+    from scenegen import configs
+    out = {}
+
+    def plain(w, W, H):
+        sc = ctx.upload_scene(w.scenes[0])
+        sn = ctx.sensor(W, H)
+        o = ctx.alloc(sn, 1)
+        poses = w.poses[:, 0]
+        for p in poses[:5]:
+            ctx.render_plain(sc, sn, p, o["rgb"], o["depth"])
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for p in poses:
+            t1 = time.perf_counter()
+            ctx.render_plain(sc, sn, p, o["rgb"], o["depth"])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+        el = time.perf_counter() - t0
+        ctx.release(sc)
+        lat = np.array(lat) * 1e3
+        return {"frames_per_s": round(len(poses) / el, 1), "views": int(len(poses)),
+                "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                "triangles": int(w.scenes[0].num_triangles), "resolution": [W, H],
+                "path": "hab_render, one view per call, synchronised per view"}
+
+    out["room_2k_128"] = plain(configs.room_2k_128(), 128, 128)
+    log(f"room_2k_128 plain: {out['room_2k_128']['frames_per_s']} frames/s")
+    out["apartment_200k_256"] = plain(configs.apartment_200k_256(), 256, 256)
+    log(f"apartment_200k_256 plain: {out['apartment_200k_256']['frames_per_s']} frames/s")
+
+    steps = max(10, min(a.steps, 50))
+    w = configs.batch256_16scenes_mixed(steps=steps + 5)
+    hs = [ctx.upload_scene(s) for s in w.scenes]
+    sensors = {}
+    for s in w.env_sensor:
+        if (s.width, s.outputs) not in sensors:
+            sensors[(s.width, s.outputs)] = ctx.sensor(s.width, s.height, s.hfov_deg, s.near_m, s.outputs)
+    items = []
+    for e in range(w.num_envs):
+        sn = sensors[(w.env_sensor[e].width, w.env_sensor[e].outputs)]
+        o = ctx.alloc(sn, 1)
+        items.append((hs[w.env_scene[e]], sn, w.poses[0, e], o.get("rgb"), o.get("depth"), None))
+    ctx.autotune(items)
+    st = ctx.stepper(items)
+    for s_ in range(5):
+        st.step(w.poses[s_])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        st.step(w.poses[5 + s_])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st.close()
+    for h in hs:
+        ctx.release(h)
+    px = sum(s.width * s.height for s in w.env_sensor)
+    out["batch256_16scenes_mixed"] = {
+        "frames_per_s": round(w.num_envs * steps / el, 1), "ms_per_step": round(1e3 * el / steps, 4),
+        "pixels_per_s": round(px * steps / el), "envs": w.num_envs, "scenes": len(w.scenes),
+        "triangles": [int(s.num_triangles) for s in w.scenes], "steps": steps,
+        "path": "HIP-graph stepper, autotuned", "sensors": "128/256/512 px x D/RGB/RGB+D per environment"}
+    log(f"batch256_16scenes_mixed graph: {out['batch256_16scenes_mixed']['frames_per_s']} frames/s")
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -95,6 +167,8 @@ def main():
     ap.add_argument("--latency-steps", type=int, default=100)
     ap.add_argument("--cpu-views", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the room / apartment-walk / mixed-batch lines")
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the batched path (warmup + steps), for profiler runs")
@@ -280,6 +354,9 @@ def main():
            "frac_of_measured_copy": round(step_bytes / (ms_step * 1e-3) / 1e9 / copy_gbs, 5)}
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
 
+    # ---------------------------------------------------- the other workloads
+    others = {} if a.no_other_workloads else other_workloads(ctx, a)
+
     # ---------------------------------------------------- CPU oracle baseline
     cpu = None
     if not a.no_cpu_baseline and a.cpu_views > 0:
@@ -343,6 +420,7 @@ def main():
         "roofline": roof,
         "hbm_roofline": hbm,
         "cpu_baseline": cpu,
+        "other_workloads": others,
         "paper_context": {"rgbd_256_fps_1proc": 1042, "rgbd_256_fps_5proc": 1774,
                           "hardware": "Titan Xp + Xeon E5-2690 v4, OpenGL, Matterport3D scene"},
     }
