@@ -488,8 +488,10 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
         const DView &v = views[vi];
         const uint32_t cnt = ctr[vi].surv_count;
         const uint32_t s0 = (item - pre[vi]) * kBinChunk;
-        const uint32_t ts = v.ts_log2;
-        const uint32_t nt = v.tiles_x * v.tiles_y;
+        // the view's fields in registers: the atomics below may not be
+        // assumed to leave the view records alone
+        const uint32_t ts = v.ts_log2, tiles_x = v.tiles_x, nt = v.tiles_x * v.tiles_y;
+        const uint32_t tile_base = v.tile_base, bin_base = v.bin_base, surv_base = v.surv_base;
         if (nt <= kLdsTiles) {
             for (uint32_t i = tid; i < nt; i += kBinBlock) hist[i] = 0;
             __syncthreads();
@@ -499,20 +501,37 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
             for (int r = 0; r < kBinItems; ++r) {
                 const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
                 if (s >= cnt) break;
-                const TileRange R = tile_range(sbox[v.surv_base + s], ts);
+                const TileRange R = tile_range(sbox[surv_base + s], ts);
                 for (int ty = R.ty0; ty <= R.ty1; ++ty)
-                    for (int tx = R.tx0; tx <= R.tx1; ++tx) atomicAdd(&hist[(uint32_t)ty * v.tiles_x + (uint32_t)tx], 1u);
+                    for (int tx = R.tx0; tx <= R.tx1; ++tx) atomicAdd(&hist[(uint32_t)ty * tiles_x + (uint32_t)tx], 1u);
             }
             __syncthreads();
-            // one global operation per touched tile
-            for (uint32_t i = tid; i < nt; i += kBinBlock) {
-                const uint32_t c = hist[i] & 0xFFFFu;
-                if (!c) continue;
-                if (!SCATTER) {
-                    atomicAdd(&tile_count[v.tile_base + i], c);
-                } else {
-                    const uint32_t off = tile_off[v.tile_base + i];
-                    lbase[i] = off == kOverflow ? kOverflow : off + atomicAdd(&tile_cursor[v.tile_base + i], c);
+            // one global operation per touched tile; a thread's tiles are
+            // i, i + kBinBlock, ...: their loads and atomics are issued
+            // together, not one tile after another
+            if (!SCATTER) {
+                for (uint32_t i = tid; i < nt; i += kBinBlock) {
+                    const uint32_t c = hist[i] & 0xFFFFu;
+                    if (c) atomicAdd(&tile_count[tile_base + i], c);
+                }
+            } else {
+                constexpr int kPer = kLdsTiles / kBinBlock;
+                uint32_t c[kPer], off[kPer], got[kPer];
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t i = tid + (uint32_t)k * kBinBlock;
+                    c[k] = i < nt ? hist[i] & 0xFFFFu : 0u;
+                    off[k] = i < nt ? tile_off[tile_base + i] : kOverflow;
+                }
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t i = tid + (uint32_t)k * kBinBlock;
+                    got[k] = (c[k] && off[k] != kOverflow) ? atomicAdd(&tile_cursor[tile_base + i], c[k]) : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t i = tid + (uint32_t)k * kBinBlock;
+                    if (c[k]) lbase[i] = off[k] == kOverflow ? kOverflow : off[k] + got[k];
                 }
             }
             if (SCATTER) {
@@ -521,15 +540,15 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                 for (int r = 0; r < kBinItems; ++r) {
                     const uint32_t s = s0 + (uint32_t)r * kBinBlock + tid;
                     if (s >= cnt) break;
-                    const TileRange R = tile_range(sbox[v.surv_base + s], ts);
-                    const uint32_t key = skey[v.surv_base + s];
+                    const TileRange R = tile_range(sbox[surv_base + s], ts);
+                    const uint32_t key = skey[surv_base + s];
                     for (int ty = R.ty0; ty <= R.ty1; ++ty)
                         for (int tx = R.tx0; tx <= R.tx1; ++tx) {
-                            const uint32_t tl = (uint32_t)ty * v.tiles_x + (uint32_t)tx;
+                            const uint32_t tl = (uint32_t)ty * tiles_x + (uint32_t)tx;
                             const uint32_t b = lbase[tl];
                             if (b == kOverflow) continue;
                             const uint32_t rank = atomicAdd(&hist[tl], 1u << 16) >> 16;
-                            bins[v.bin_base + b + rank] = key;
+                            bins[bin_base + b + rank] = key;
                         }
                 }
             }
