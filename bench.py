@@ -31,6 +31,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic VALU work of the raster stage: 8 ops per bbox pixel test (three
 # edge functions at 2 ops, a combine, a compare) and 12 more per covered
 # fragment (three int->float, four multiplies, two adds, compare/select)
+RASTER_PHASES = ("raster8", "raster16", "raster32")
 OPS_PER_TEST = 8
 OPS_PER_COVERED = 12
 
@@ -241,6 +242,16 @@ def main():
     for s in range(a.warmup):
         batch_step(s)
     torch.cuda.synchronize()
+    # per-phase breakdown: every phase timed, over the same poses, untimed
+    ctx.profile_phases(None)
+    ctx.profile(True)
+    for s in range(a.steps):
+        batch_step(s)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    phases = ctx.profile_read()
+    # the timed steps: HIP events only around the raster launches
+    ctx.profile_phases(RASTER_PHASES)
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -249,7 +260,10 @@ def main():
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     ctx.profile(False)
-    phases = ctx.profile_read()
+    timed = ctx.profile_read()
+    ctx.profile_phases(None)
+    for k, v in timed.items():
+        phases[k] = v      # the dominant kernel's time is the one taken in the timed steps
     fps_batch = E * a.steps / t_batch
     log(f"batched eager: {fps_batch:.0f} frames/s ({1e3 * t_batch / a.steps:.3f} ms/step)")
     log("phases (ms/step): " + ", ".join(f"{k}={v['ms'] / max(v['launches'], 1):.4f}"

@@ -256,6 +256,10 @@ typedef struct {
     uint64_t sequences;                /* launch sequences that were timed    */
 } hab_phase_times;
 hab_status hab_profile_enable(hab_context *ctx, int on);
+/* Restrict the timed phases to bit set `phase_mask` (bit k = phase k; the
+ * default is all): fewer events are recorded, so timing perturbs the rest
+ * of the step less.  HAB_ERR_INVALID_ARG for a mask with no phase. */
+hab_status hab_profile_phases(hab_context *ctx, uint32_t phase_mask);
 /* Synchronise, add up every timed sequence since the last read, reset. */
 hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out);
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "hab_stepper_create", "hab_stepper_step", "hab_stepper_destroy",
     "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
-    "hab_profile_enable", "hab_profile_read",
+    "hab_profile_enable", "hab_profile_phases", "hab_profile_read",
 ]
 PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "raster16",
           "raster32", "resolve"]
@@ -147,6 +147,7 @@ def load():
             "hab_server_destroy": [vp],
             "hab_autotune": [vp, C.POINTER(View), u32, vp, C.POINTER(u32), C.POINTER(f32)],
             "hab_profile_enable": [vp, C.c_int],
+            "hab_profile_phases": [vp, C.c_uint32],
             "hab_profile_read": [vp, C.POINTER(PhaseTimes)],
         }
         for name, args in sig.items():

@@ -357,6 +357,13 @@ hab_status hab_profile_enable(hab_context *ctx, int on)
     return HAB_OK;
 }
 
+hab_status hab_profile_phases(hab_context *ctx, uint32_t phase_mask)
+{
+    if (!ctx || !(phase_mask & ((1u << HAB_NUM_PHASES) - 1u))) return HAB_ERR_INVALID_ARG;
+    ctx->prof_phase_mask = phase_mask & ((1u << HAB_NUM_PHASES) - 1u);
+    return HAB_OK;
+}
+
 hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out)
 {
     if (!ctx || !out) return HAB_ERR_INVALID_ARG;

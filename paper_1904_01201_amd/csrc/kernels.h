@@ -48,6 +48,7 @@ struct LaunchPlan {
     RasterLaunch raster[3];
     int nraster;
     hipEvent_t *prof;          // null, or kProfEvents events recorded around the kernels
+    uint32_t prof_mask;        // phases whose start/stop events are recorded
 };
 
 constexpr int kPhaseResolve = 8;

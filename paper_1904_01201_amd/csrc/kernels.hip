@@ -1139,7 +1139,7 @@ static inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 static inline void mark(const LaunchPlan &L, int ev, hipStream_t s)
 {
-    if (L.prof) (void)hipEventRecord(L.prof[ev], s);
+    if (L.prof && ((L.prof_mask >> (ev >> 1)) & 1u)) (void)hipEventRecord(L.prof[ev], s);
 }
 
 template <int TS>

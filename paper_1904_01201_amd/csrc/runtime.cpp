@@ -422,7 +422,9 @@ hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint3
         for (int k = 0; k < plan.L.nraster; ++k)
             if (plan.L.raster[k].blocks)
                 ps->mask |= 1u << (plan.L.raster[k].ts == 8 ? 5 : plan.L.raster[k].ts == 16 ? 6 : 7);
+        ps->mask &= ctx->prof_phase_mask;
         plan.L.prof = ps->ev;
+        plan.L.prof_mask = ps->mask;
     }
     HAB_HIP(launch_render(plan.L, s));
     HAB_HIP(hipEventRecord(ws.done, s));

@@ -121,6 +121,7 @@ struct hab_context {
         uint32_t mask;            // phases recorded in this set
     };
     bool prof_on = false;
+    uint32_t prof_phase_mask = 0x1FFu;   // phases timed while profiling is on
     std::vector<ProfSet> prof_sets;
     size_t prof_used = 0;
 };

@@ -216,6 +216,11 @@ class Context:
     def profile(self, on: bool = True):
         B.check(self.lib.hab_profile_enable(self.h, 1 if on else 0), "hab_profile_enable")
 
+    def profile_phases(self, names=None):
+        """Time only the named phases (None: all)."""
+        mask = (1 << len(B.PHASES)) - 1 if names is None else sum(1 << B.PHASES.index(n) for n in names)
+        B.check(self.lib.hab_profile_phases(self.h, mask), "hab_profile_phases")
+
     def profile_read(self):
         """Per-phase summed device ms and launch counts since the last read."""
         t = B.PhaseTimes()

@@ -69,6 +69,7 @@ def test_null_arguments(lib):
     assert lib.hab_render(None, None, None, None, 0, None, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_render_batch(None, None, 0, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_stepper_step(None, None, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_profile_phases(None, 1) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_server_submit(None, None, None) == B.HAB_ERR_INVALID_ARG
 
 

@@ -192,6 +192,29 @@ def test_plain_entry_point(ctx):
     ctx.release(sc)
 
 
+def test_profile_phase_mask(ctx):
+    """Only the selected phases are timed; an empty selection is refused."""
+    import paper_1904_01201_amd as P
+    note("profile phase mask")
+    w = configs.room_2k_128()
+    sc = ctx.upload_scene(w.scenes[0])
+    s = ctx.sensor(128, 128)
+    ctx.profile_phases(["raster8", "raster16", "raster32"])
+    ctx.profile(True)
+    ctx.render(sc, s, w.poses[:4, 0], tile_size=8)
+    ctx.profile(False)
+    ph = ctx.profile_read()
+    ctx.profile_phases(None)
+    assert set(ph) == {"raster8"} and ph["raster8"]["launches"] == 1, ph
+    ctx.profile(True)
+    ctx.render(sc, s, w.poses[:4, 0], tile_size=8)
+    ctx.profile(False)
+    assert {"reset", "setup", "raster8", "resolve"} <= set(ctx.profile_read())
+    with pytest.raises(P.HabError):
+        ctx.profile_phases([])
+    ctx.release(sc)
+
+
 def test_argument_errors(ctx):
     import paper_1904_01201_amd as P
     note("argument errors")
