@@ -790,6 +790,29 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     x.ny0 = -dy[0];
     x.ny1 = -dy[1];
     x.ny2 = -dy[2];
+    if constexpr (TS == 8) {
+        // Drop the quarters that hold no pixel centre the triangle can
+        // cover: an edge whose largest value over a quarter's centres is
+        // below its threshold (1 if not owned, else 0) excludes the quarter.
+        // Exact in int32 for packed records (|E| <= 2^29 over the tile).
+        if (packed) {
+            QMask<TS> keep = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int P0 = 256 * 4 * (q & 1), Q0 = 256 * 4 * (q >> 1);
+                bool ok = (qm >> q) & 1u;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int emax = (int)C[k] + dx[k] * (dx[k] > 0 ? Q0 + 768 : Q0) -
+                                     dy[k] * (dy[k] < 0 ? P0 + 768 : P0);
+                    ok = ok && emax >= (int)((notown >> (8 * k)) & 1u);
+                }
+                if (ok) keep |= 1u << q;
+            }
+            qm = keep;
+            if (!qm) return false;
+        }
+    }
     r.invA = 1.0f / (float)A;
     r.rw0 = a.rw;
     r.rw1 = b.rw;
