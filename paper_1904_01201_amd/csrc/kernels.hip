@@ -751,33 +751,56 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     const int dy[3] = {c.Y - b.Y, a.Y - c.Y, b.Y - a.Y};
     const int ax[3] = {b.X, c.X, a.X};
     const int ay[3] = {b.Y, c.Y, a.Y};
-    const long long Ox = 256ll * ti0 + 128, Oy = 256ll * tj0 + 128;
-    constexpr long long PM = 256ll * (TS - 1);
-    long long C[3];
     uint32_t notown = 0;
-    bool fast = true;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        C[k] = (long long)dx[k] * (Oy - ay[k]) - (long long)dy[k] * (Ox - ax[k]);
+    for (int k = 0; k < 3; ++k)
         if (!owned(dx[k], dy[k])) notown |= 1u << (8 * k);
-        const long long qx = (long long)dx[k] * PM, px = -(long long)dy[k] * PM;
-        const long long emax = C[k] + (qx > 0 ? qx : 0) + (px > 0 ? px : 0);
-        const long long emin = C[k] + (qx < 0 ? qx : 0) + (px < 0 ? px : 0);
-        // every pixel value of the tile within +-2^29, so each product term
-        // (a difference of two such values) stays within +-2^30: no int32
-        // intermediate can overflow
-        fast = fast && emax <= (1ll << 29) && emin >= -(1ll << 29) &&
-               dx[k] < (1 << 22) && dx[k] > -(1 << 22) && dy[k] < (1 << 22) && dy[k] > -(1 << 22);
-    }
-    bool packed = fast;
+    // C_k = E_k at the tile's first pixel centre, as low and high words
+    int clo[3], chi[3];
+    bool fast = true, packed = true;
+    // edge start points relative to that centre (|X| < 2^29: fits int32)
+    const int Ox = 256 * ti0 + 128, Oy = 256 * tj0 + 128;
+    const int rx[3] = {ax[0] - Ox, ax[1] - Ox, ax[2] - Ox};
+    const int ry[3] = {ay[0] - Oy, ay[1] - Oy, ay[2] - Oy};
+    constexpr int kNear = 1 << 14;
+    const bool small = abs(rx[0]) < kNear && abs(rx[1]) < kNear && abs(rx[2]) < kNear && abs(ry[0]) < kNear &&
+                       abs(ry[1]) < kNear && abs(ry[2]) < kNear;
+    if (small) {
+        // every vertex within 64 px of the tile: |d| < 2^15, 24-bit products,
+        // |C| < 2^30, every pixel value of the tile < 2^31 in magnitude:
+        // the packed form, without 64-bit arithmetic
 #pragma unroll
-    for (int k = 0; k < 3; ++k) packed = packed && dx[k] < 32768 && dx[k] > -32768 && dy[k] < 32768 && dy[k] > -32768;
-    r.c0 = (int)(uint32_t)(unsigned long long)C[0];
-    r.c1 = (int)(uint32_t)(unsigned long long)C[1];
-    r.c2 = (int)(uint32_t)(unsigned long long)C[2];
-    x.hi0 = (int)(C[0] >> 32);
-    x.hi1 = (int)(C[1] >> 32);
-    x.hi2 = (int)(C[2] >> 32);
+        for (int k = 0; k < 3; ++k) {
+            clo[k] = __mul24(dy[k], rx[k]) - __mul24(dx[k], ry[k]);
+            chi[k] = clo[k] >> 31;
+        }
+    } else {
+        constexpr long long PM = 256ll * (TS - 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const long long C = (long long)dx[k] * ((long long)Oy - ay[k]) - (long long)dy[k] * ((long long)Ox - ax[k]);
+            clo[k] = (int)(uint32_t)(unsigned long long)C;
+            chi[k] = (int)(C >> 32);
+            const long long qx = (long long)dx[k] * PM, px = -(long long)dy[k] * PM;
+            const long long emax = C + (qx > 0 ? qx : 0) + (px > 0 ? px : 0);
+            const long long emin = C + (qx < 0 ? qx : 0) + (px < 0 ? px : 0);
+            // every pixel value of the tile within +-2^29, so each product
+            // term (a difference of two such values) stays within +-2^30: no
+            // int32 intermediate can overflow
+            fast = fast && emax <= (1ll << 29) && emin >= -(1ll << 29) && dx[k] < (1 << 22) &&
+                   dx[k] > -(1 << 22) && dy[k] < (1 << 22) && dy[k] > -(1 << 22);
+        }
+        packed = fast;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            packed = packed && dx[k] < 32768 && dx[k] > -32768 && dy[k] < 32768 && dy[k] > -32768;
+    }
+    r.c0 = clo[0];
+    r.c1 = clo[1];
+    r.c2 = clo[2];
+    x.hi0 = chi[0];
+    x.hi1 = chi[1];
+    x.hi2 = chi[2];
     if (packed) {
         r.e0 = (int)(((uint32_t)dx[0] & 0xFFFFu) | ((uint32_t)(-dy[0]) << 16));
         r.e1 = (int)(((uint32_t)dx[1] & 0xFFFFu) | ((uint32_t)(-dy[1]) << 16));
@@ -794,7 +817,7 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
         // Drop the quarters that hold no pixel centre the triangle can
         // cover: an edge whose largest value over a quarter's centres is
         // below its threshold (1 if not owned, else 0) excludes the quarter.
-        // Exact in int32 for packed records (|E| <= 2^29 over the tile).
+        // Exact in int32 for packed records (|E| < 2^31 over the tile).
         if (packed) {
             QMask<TS> keep = 0;
 #pragma unroll
@@ -803,8 +826,8 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
                 bool ok = (qm >> q) & 1u;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const int emax = (int)C[k] + dx[k] * (dx[k] > 0 ? Q0 + 768 : Q0) -
-                                     dy[k] * (dy[k] < 0 ? P0 + 768 : P0);
+                    const int emax = clo[k] + __mul24(dx[k], dx[k] > 0 ? Q0 + 768 : Q0) -
+                                     __mul24(dy[k], dy[k] < 0 ? P0 + 768 : P0);
                     ok = ok && emax >= (int)((notown >> (8 * k)) & 1u);
                 }
                 if (ok) keep |= 1u << q;
