@@ -80,7 +80,7 @@ typedef struct hab_server hab_server;
 
 /* Triangle mesh on the host.  positions [V][3] float (metres), colors
  * [V][3] uint8 RGB (NULL: all white), indices [T][3] uint32 (each < V).
- * V >= 1, T < 2^30. */
+ * 1 <= V < 2^30, T < 2^30 (HAB_ERR_INVALID_ARG otherwise). */
 typedef struct {
     const float *positions;
     uint32_t num_vertices;

@@ -129,7 +129,7 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
 {
     if (!ctx || !m || !out) return HAB_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!m->positions || m->num_vertices == 0) return HAB_ERR_INVALID_ARG;
+    if (!m->positions || m->num_vertices == 0 || m->num_vertices >= (1u << 30)) return HAB_ERR_INVALID_ARG;
     if (m->num_triangles >= (1u << 30)) return HAB_ERR_INVALID_ARG;
     if (m->num_triangles && !m->indices) return HAB_ERR_INVALID_ARG;
     return guarded([&]() -> hab_status {

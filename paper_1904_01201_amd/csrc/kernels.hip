@@ -127,13 +127,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gmem_out(T *p)
 
 __device__ __forceinline__ void load_tri(const DView &v, uint32_t t, float P[9], uint32_t vid[3])
 {
-    const auto *ix = gmem(v.idx) + 3ull * t;
+    // T, V < 2^30 (checked at upload): 32-bit element offsets
+    const auto *ix = gmem(v.idx) + 3u * t;
     vid[0] = ix[0];
     vid[1] = ix[1];
     vid[2] = ix[2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const auto *p = gmem(v.pos) + 3ull * vid[k];
+        const auto *p = gmem(v.pos) + 3u * vid[k];
         P[3 * k + 0] = p[0];
         P[3 * k + 1] = p[1];
         P[3 * k + 2] = p[2];
@@ -836,7 +837,12 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
             if (!qm) return false;
         }
     }
-    r.invA = 1.0f / (float)A;
+    // (float)A: from int32 when A fits (always for small records), which is
+    // the same rounding as the int64 conversion
+    float fA;
+    if (A == (long long)(int)A) fA = (float)(int)A;
+    else fA = (float)A;
+    r.invA = 1.0f / fA;
     r.rw0 = a.rw;
     r.rw1 = b.rw;
     r.rw2 = c.rw;
