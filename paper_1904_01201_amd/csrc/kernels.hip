@@ -733,7 +733,30 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     cam_xform(v, P[6], P[7], P[8], c2);
     SVtx<0> a, b, c;
     long long A;
-    if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) return false;
+    if (c0.w >= v.zn && c1.w >= v.zn && c2.w >= v.zn) {
+        // all three vertices in front of the near plane (the common case):
+        // clipping returns them unchanged and there is no second
+        // sub-triangle, so this is the setup of sub-triangle 0 without the
+        // polygon bookkeeping
+        if (sub != 0) return false;
+        bool ok = snap(v, c0, a);
+        ok &= snap(v, c1, b);
+        ok &= snap(v, c2, c);
+        if (!ok) {
+            rerr = true;
+            return false;
+        }
+        A = area2(a, b, c);
+        if (A == 0) return false;
+        if (A < 0) {
+            const SVtx<0> tmp = b;
+            b = c;
+            c = tmp;
+            A = -A;
+        }
+    } else if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) {
+        return false;
+    }
     const PixBox pb = pix_box(v, a, b, c);
     const int bi0 = max(pb.i0 - ti0, 0), bi1 = min(pb.i1 - ti0, TS - 1);
     const int bj0 = max(pb.j0 - tj0, 0), bj1 = min(pb.j1 - tj0, TS - 1);
