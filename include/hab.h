@@ -71,7 +71,10 @@ typedef enum {
 #define HAB_NO_HIT 0xFFFFFFFFu
 #define HAB_MAX_DIM 4096u
 
-enum { HAB_OUT_RGB = 1, HAB_OUT_DEPTH = 2, HAB_OUT_TRI = 4 };
+/* Outputs of a sensor.  HAB_OUT_SEMANTIC: the instance id of the visible
+ * triangle (the semantic attachment of the paper's single render pass,
+ * Sec. 3 "Rendering engine"), from the scene's per-triangle instance table. */
+enum { HAB_OUT_RGB = 1, HAB_OUT_DEPTH = 2, HAB_OUT_TRI = 4, HAB_OUT_SEMANTIC = 8 };
 
 typedef struct hab_context hab_context;
 typedef struct hab_scene hab_scene;
@@ -79,14 +82,17 @@ typedef struct hab_stepper hab_stepper;
 typedef struct hab_server hab_server;
 
 /* Triangle mesh on the host.  positions [V][3] float (metres), colors
- * [V][3] uint8 RGB (NULL: all white), indices [T][3] uint32 (each < V).
- * 1 <= V < 2^30, T < 2^30 (HAB_ERR_INVALID_ARG otherwise). */
+ * [V][3] uint8 RGB (NULL: all white), indices [T][3] uint32 (each < V),
+ * instances [T] uint32 instance id per triangle (NULL: the scene has no
+ * semantic table and cannot feed HAB_OUT_SEMANTIC).  1 <= V < 2^30,
+ * T < 2^30 (HAB_ERR_INVALID_ARG otherwise). */
 typedef struct {
     const float *positions;
     uint32_t num_vertices;
     const uint8_t *colors;
     const uint32_t *indices;
     uint32_t num_triangles;
+    const uint32_t *instances;
 } hab_mesh_desc;
 
 /* Sensor request.  width, height in [1, 4096]; hfov_deg in (0, 180);
@@ -137,7 +143,10 @@ typedef struct {
 } hab_render_opts;
 
 /* One view of a heterogeneous batch: any scene, any sensor, own outputs
- * (device pointers sized for that sensor; NULL for unwanted outputs). */
+ * (device pointers sized for that sensor; NULL for unwanted outputs).
+ * out_semantic ([H][W] uint32, HAB_NO_HIT where nothing is visible) is
+ * written when the sensor has HAB_OUT_SEMANTIC; the scene must then have an
+ * instance table (else HAB_ERR_INVALID_ARG). */
 typedef struct {
     const hab_scene *scene;
     const hab_sensor *sensor;
@@ -145,6 +154,7 @@ typedef struct {
     uint8_t *out_rgb;
     float *out_depth;
     uint32_t *out_tri;
+    uint32_t *out_semantic;
 } hab_view;
 
 /* ---------------------------------------------------------- lifetime */
@@ -184,14 +194,16 @@ hab_status hab_render(hab_context *ctx, const hab_scene *scene, const hab_sensor
                       float *out_depth, hipStream_t stream);
 /* As hab_render, plus the visible-triangle output (device [N][H][W]
  * uint32 or NULL) and options (NULL = defaults).  With opts->stats set
- * the call synchronises the stream before returning. */
+ * the call synchronises the stream before returning.  hab_render and
+ * hab_render_ex have no semantic output: they ignore HAB_OUT_SEMANTIC
+ * (hab_view carries it, for hab_render_batch, the stepper and the server). */
 hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
                          const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb,
                          float *out_depth, uint32_t *out_tri, const hab_render_opts *opts,
                          hipStream_t stream);
 /* Render a heterogeneous batch (different scenes, resolutions and output
- * sets) in one launch sequence.  Views of the same scene are grouped so
- * that each triangle is fetched once per group. */
+ * sets) in one launch sequence.  Views are ordered by scene, so the views
+ * of one scene read its geometry while it is in cache. */
 hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t num_views,
                             const hab_render_opts *opts, hipStream_t stream);
 

@@ -102,10 +102,28 @@ def pose_check(lo, hi, pose, W, H, hfov_deg=90.0, near_m=0.01) -> int:
                                      _ptr(pose, C.c_float), W, H, hfov_deg, near_m))
 
 
+def semantic_image(tri, instances):
+    """Semantic instance mask (the third attachment of the single render
+    pass, Sec. 3 "Rendering engine"; the RGB + depth + semantics row of the
+    performance table in the appendix on platform details): each pixel holds
+    the instance id of the object its visible triangle belongs to, NONE where
+    no triangle is visible."""
+    tri = np.asarray(tri, np.uint32)
+    inst = np.asarray(instances, np.uint32).reshape(-1)
+    out = np.full(tri.shape, NONE, np.uint32)
+    for j in range(tri.shape[0]):
+        for i in range(tri.shape[1]):
+            t = int(tri[j, i])
+            if t != NONE:
+                out[j, i] = inst[t]
+    return out
+
+
 def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.01,
-                raw=False):
+                raw=False, instances=None):
     """Render one view.  Returns dict(rgb [H,W,3] u8, depth [H,W] f32,
-    tri [H,W] u32, stats) and, with ``raw``, rho [H,W] f32 and key [H,W] u32.
+    tri [H,W] u32, stats), with ``instances`` ([T] u32 per-triangle ids) also
+    semantic [H,W] u32, and with ``raw`` rho [H,W] f32 and key [H,W] u32.
     Raises on a non-OK status."""
     pos, col, idx = _geom(positions, colors, indices)
     pose = np.ascontiguousarray(pose, np.float32).reshape(12)
@@ -123,6 +141,8 @@ def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.
     if rc != OR_OK:
         raise OracleError(rc)
     out = {"rgb": rgb, "depth": depth, "tri": tri, "stats": st.as_dict()}
+    if instances is not None:
+        out["semantic"] = semantic_image(tri, instances)
     if raw:
         out["rho"] = rho
         out["key"] = key

@@ -6,12 +6,12 @@ ABI of include/hab.h); this package is its ctypes binding.  Importing the
 package does not load the library; the first Context does, and raises if
 it has not been built.
 """
-from .binding import (HabError, OUT_RGB, OUT_DEPTH, OUT_TRI, HAB_NO_HIT, HAB_OK,
+from .binding import (HabError, OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC, HAB_NO_HIT, HAB_OK,
                       HAB_ERR_INVALID_ARG, HAB_ERR_OUT_OF_MEMORY, HAB_ERR_RANGE,
                       HAB_ERR_DEVICE, HAB_ERR_NOT_READY, HAB_ERR_CAPACITY, load, lib_path)
 from .renderer import Context, SceneHandle, Server, Stepper
 
 __all__ = ["Context", "SceneHandle", "Server", "Stepper", "HabError", "OUT_RGB", "OUT_DEPTH", "OUT_TRI",
-           "HAB_NO_HIT", "HAB_OK", "HAB_ERR_INVALID_ARG", "HAB_ERR_OUT_OF_MEMORY",
+           "OUT_SEMANTIC",           "HAB_NO_HIT", "HAB_OK", "HAB_ERR_INVALID_ARG", "HAB_ERR_OUT_OF_MEMORY",
            "HAB_ERR_RANGE", "HAB_ERR_DEVICE", "HAB_ERR_NOT_READY", "HAB_ERR_CAPACITY", "load",
            "lib_path"]

@@ -24,7 +24,7 @@ HAB_ERR_DEVICE = 4
 HAB_ERR_NOT_READY = 5
 HAB_ERR_CAPACITY = 6
 HAB_NO_HIT = 0xFFFFFFFF
-OUT_RGB, OUT_DEPTH, OUT_TRI = 1, 2, 4
+OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC = 1, 2, 4, 8
 
 EXPORTED = [
     "hab_init", "hab_shutdown", "hab_status_string", "hab_get_error",
@@ -41,7 +41,8 @@ PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "
 
 class MeshDesc(C.Structure):
     _fields_ = [("positions", C.c_void_p), ("num_vertices", C.c_uint32),
-                ("colors", C.c_void_p), ("indices", C.c_void_p), ("num_triangles", C.c_uint32)]
+                ("colors", C.c_void_p), ("indices", C.c_void_p), ("num_triangles", C.c_uint32),
+                ("instances", C.c_void_p)]
 
 
 class SensorDesc(C.Structure):
@@ -69,7 +70,8 @@ class RenderOpts(C.Structure):
 
 class View(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("sensor", C.POINTER(Sensor)), ("pose", Pose),
-                ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_tri", C.c_void_p)]
+                ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_tri", C.c_void_p),
+                ("out_semantic", C.c_void_p)]
 
 
 class ServerCfg(C.Structure):

@@ -100,6 +100,7 @@ hab_status hab_shutdown(hab_context *ctx)
             (void)hipFree(s->col);
             (void)hipFree(s->idx);
             (void)hipFree(s->cbox);
+            (void)hipFree(s->inst);
             delete static_cast<hab_scene *>(s);
         }
         ctx->scenes.clear();
@@ -182,28 +183,33 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
         }
         const size_t bp = 12ull * V, bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
         const size_t bb = sizeof(float4) * cbox.size();
+        const size_t bs = m->instances ? std::max<size_t>(4ull * T, 4) : 0;
         auto drop = [&]() {
             (void)hipFree(s->pos);
             (void)hipFree(s->col);
             (void)hipFree(s->idx);
             (void)hipFree(s->cbox);
+            (void)hipFree(s->inst);
             delete s;
         };
         bool ok = hipMalloc((void **)&s->pos, bp) == hipSuccess &&
                   hipMalloc((void **)&s->col, bc) == hipSuccess &&
                   hipMalloc((void **)&s->idx, bi) == hipSuccess &&
-                  hipMalloc((void **)&s->cbox, bb) == hipSuccess;
+                  hipMalloc((void **)&s->cbox, bb) == hipSuccess &&
+                  (!bs || hipMalloc((void **)&s->inst, bs) == hipSuccess);
         if (!ok) {
             (void)hipGetLastError();
             drop();
             return HAB_ERR_OUT_OF_MEMORY;
         }
-        s->bytes = bp + bc + bi + bb;
+        s->bytes = bp + bc + bi + bb + bs;
         hipError_t e = hipMemcpyAsync(s->pos, m->positions, bp, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s->col, col.data(), bc, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && T)
             e = hipMemcpyAsync(s->idx, m->indices, 12ull * T, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s->cbox, cbox.data(), bb, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && bs && T)
+            e = hipMemcpyAsync(s->inst, m->instances, 4ull * T, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
             drop();
@@ -228,6 +234,7 @@ hab_status hab_scene_release(hab_context *ctx, hab_scene *scene)
         (void)hipFree(scene->col);
         (void)hipFree(scene->idx);
         (void)hipFree(scene->cbox);
+        (void)hipFree(scene->inst);
         ctx->scenes.erase(it);
         delete scene;
         return HAB_OK;
@@ -257,7 +264,8 @@ hab_status hab_sensor_spec(const hab_sensor_desc *d, hab_sensor *out)
     const float near_m = d->near_m == 0.0f ? 0.01f : d->near_m;
     if (!(near_m > 0.0f) || !std::isfinite(near_m)) return HAB_ERR_INVALID_ARG;
     const uint32_t outputs = d->outputs ? d->outputs : (HAB_OUT_RGB | HAB_OUT_DEPTH);
-    if (outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI)) return HAB_ERR_INVALID_ARG;
+    if (outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI | HAB_OUT_SEMANTIC))
+        return HAB_ERR_INVALID_ARG;
     hab_sensor s;
     s.width = d->width;
     s.height = d->height;

@@ -17,7 +17,7 @@ constexpr int kCluster = 64;                  // triangles per culling cluster (
 constexpr uint32_t kErrRange = 1u;            // a vertex snapped outside |X|,|Y| < 2^29
 constexpr uint32_t kErrResolve = 2u;          // a winning key could not be rebuilt
 
-// One view of a launch.  16-byte aligned; 192 bytes.
+// One view of a launch.  16-byte aligned; 224 bytes.
 struct alignas(16) DView {
     float p[3];
     float R[9];                 // row-major world-from-camera
@@ -42,8 +42,11 @@ struct alignas(16) DView {
     const float4 *cbox;         // per 64-triangle cluster: (min xyz, -) (max xyz, -)
     uint32_t count_work;        // 1: accumulate bbox tests and covered fragments
     uint32_t pad;
+    const uint32_t *inst;       // [T] instance id per triangle (semantic output)
+    uint32_t *sem;              // [H][W] or null
+    uint32_t pad2[4];
 };
-static_assert(sizeof(DView) == 192, "DView layout");
+static_assert(sizeof(DView) == 224, "DView layout");
 
 // Work queues of the raster stage, per tile size (8, 16, 32): `total`
 // items were appended by the scan.  The items are dealt to kQueues queues

@@ -1207,6 +1207,7 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
     }
     if (v.depth) gmem_out(v.depth)[p] = depth;
     if (v.tri) gmem_out(v.tri)[p] = best_key == kNone ? kNone : (best_key >> 1);
+    if (v.sem) gmem_out(v.sem)[p] = best_key == kNone ? kNone : gmem(v.inst)[best_key >> 1];
 }
 
 // ------------------------------------------------------------ host side

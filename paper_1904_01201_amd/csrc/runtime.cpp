@@ -92,7 +92,8 @@ hab_status validate_sensor(const hab_sensor *s)
         return HAB_ERR_INVALID_ARG;
     if (!(s->hfov_deg > 0.0f && s->hfov_deg < 180.0f)) return HAB_ERR_INVALID_ARG;
     if (!(s->near_m > 0.0f) || !std::isfinite(s->near_m)) return HAB_ERR_INVALID_ARG;
-    if (s->outputs == 0 || (s->outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI)))
+    if (s->outputs == 0 ||
+        (s->outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI | HAB_OUT_SEMANTIC)))
         return HAB_ERR_INVALID_ARG;
     if (s->f != (float)focal_of(s->width, s->hfov_deg)) return HAB_ERR_INVALID_ARG;
     return HAB_OK;
@@ -146,6 +147,8 @@ hab_status to_view_req(const hab_view &hv, ViewReq &out)
     out.rgb = (hv.sensor->outputs & HAB_OUT_RGB) ? hv.out_rgb : nullptr;
     out.depth = (hv.sensor->outputs & HAB_OUT_DEPTH) ? hv.out_depth : nullptr;
     out.tri = hv.out_tri;
+    out.sem = (hv.sensor->outputs & HAB_OUT_SEMANTIC) ? hv.out_semantic : nullptr;
+    if (out.sem && !sc->inst) return HAB_ERR_INVALID_ARG;
     return HAB_OK;
 }
 
@@ -156,7 +159,7 @@ uint32_t class_key(const Scene *sc, const hab_sensor *s)
     while ((1u << tlog) < std::max<uint32_t>(sc->T, 1)) ++tlog;
     uint32_t wlog = 0;
     while ((1u << wlog) < std::max(s->width, s->height)) ++wlog;
-    return (tlog << 8) | (wlog << 3) | (s->outputs & 7u);
+    return (tlog << 9) | (wlog << 4) | (s->outputs & 15u);
 }
 
 uint32_t choose_tile(hab_context *ctx, const Scene *sc, const hab_sensor *s, const PlanOpts &o,
@@ -217,6 +220,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.rgb = r.rgb;
         d.depth = r.depth;
         d.tri = r.tri;
+        d.inst = r.scene->inst;
+        d.sem = r.sem;
         d.tiles_x = cdiv(d.W, ts);
         d.tiles_y = cdiv(d.H, ts);
         d.tile_base = (uint32_t)tile_total;

@@ -25,6 +25,7 @@ struct Scene {
     uint32_t *col = nullptr;    // [V] packed
     uint32_t *idx = nullptr;    // [T][3]
     float4 *cbox = nullptr;     // [ceil(T/64)][2] cluster bounding boxes
+    uint32_t *inst = nullptr;   // [T] instance id per triangle, or null
     uint32_t V = 0, T = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     uint64_t bytes = 0;
@@ -38,6 +39,7 @@ struct ViewReq {
     uint8_t *rgb;
     float *depth;
     uint32_t *tri;
+    uint32_t *sem;
 };
 
 struct PlanOpts {

@@ -41,6 +41,7 @@ class Agents:
             v.out_rgb = int(out["rgb"].data_ptr()) if "rgb" in out else None
             v.out_depth = int(out["depth"].data_ptr()) if "depth" in out else None
             v.out_tri = None
+            v.out_semantic = int(out["semantic"].data_ptr()) if "semantic" in out else None
             self.views.append(v)
             self.outs.append((sn, out))
         self.step = np.zeros(self.n, np.int64)

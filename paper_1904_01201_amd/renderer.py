@@ -27,7 +27,8 @@ def _ptr(t):
     return None if t is None else C.c_void_p(int(t.data_ptr()))
 
 
-_DT = {"rgb": "uint8", "depth": "float32", "tri": ("int32", "uint32")}
+_DT = {"rgb": "uint8", "depth": "float32", "tri": ("int32", "uint32"),
+       "semantic": ("int32", "uint32")}
 
 
 def check_output(name, t, n, sensor):
@@ -82,12 +83,20 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------ scenes
-    def upload(self, positions, colors, indices, stream=None) -> SceneHandle:
+    def upload(self, positions, colors, indices, instances=None, stream=None) -> SceneHandle:
+        """instances: optional [T] uint32 instance id per triangle (needed
+        for the semantic output)."""
         pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
         idx = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
         col = None if colors is None else np.ascontiguousarray(colors, np.uint8).reshape(-1, 3)
+        ins = None
+        if instances is not None:
+            ins = np.ascontiguousarray(instances, np.uint32).reshape(-1)
+            if ins.shape[0] != idx.shape[0]:
+                raise ValueError(f"instances: {ins.shape[0]} ids for {idx.shape[0]} triangles")
         d = B.MeshDesc(pos.ctypes.data, pos.shape[0], None if col is None else col.ctypes.data,
-                       idx.ctypes.data if idx.size else None, idx.shape[0])
+                       idx.ctypes.data if idx.size else None, idx.shape[0],
+                       ins.ctypes.data if ins is not None and ins.size else None)
         out = C.c_void_p()
         B.check(self.lib.hab_scene_upload(self.h, C.byref(d), _stream_ptr(stream), C.byref(out)),
                 "hab_scene_upload")
@@ -99,7 +108,8 @@ class Context:
         return s
 
     def upload_scene(self, scene, stream=None) -> SceneHandle:
-        return self.upload(scene.positions, scene.colors, scene.indices, stream)
+        return self.upload(scene.positions, scene.colors, scene.indices,
+                           getattr(scene, "instances", None), stream=stream)
 
     def release(self, scene: SceneHandle):
         B.check(self.lib.hab_scene_release(self.h, C.c_void_p(scene.ptr)), "hab_scene_release")
@@ -126,6 +136,8 @@ class Context:
             out["depth"] = torch.empty((n, H, W), dtype=torch.float32, device=device)
         if tri or (sensor.outputs & B.OUT_TRI):
             out["tri"] = torch.empty((n, H, W), dtype=torch.int32, device=device)
+        if sensor.outputs & B.OUT_SEMANTIC:
+            out["semantic"] = torch.empty((n, H, W), dtype=torch.int32, device=device)
         return out
 
     @staticmethod
@@ -139,7 +151,9 @@ class Context:
     def render(self, scene: SceneHandle, sensor: B.Sensor, poses, rgb=None, depth=None, tri=None,
                tile_size=0, bin_factor=0.0, tile_cap=0, stats=False, stream=None, out=None):
         """Render N views of one scene.  Returns dict of output tensors (and
-        'stats': list of dicts if requested)."""
+        'stats': list of dicts if requested).  A sensor with the semantic
+        output goes through hab_render_batch (one view per pose), since
+        hab_render_ex has no semantic output."""
         poses = np.asarray(poses, np.float32).reshape(-1, 12)
         n = poses.shape[0]
         if out is None:
@@ -152,8 +166,16 @@ class Context:
             out["tri"] = tri
         if not out:
             out = self.alloc(sensor, n, tri=False)
-        for k in ("rgb", "depth", "tri"):
+        for k in ("rgb", "depth", "tri", "semantic"):
             check_output(k, out.get(k), n, sensor)
+        if out.get("semantic") is not None:
+            items = [(scene, sensor, poses[k], *[None if out.get(name) is None else out[name][k]
+                                                 for name in ("rgb", "depth", "tri", "semantic")])
+                     for k in range(n)]
+            st = self.render_batch(items, tile_size, bin_factor, tile_cap, stats, stream)
+            if stats:
+                out["stats"] = st
+            return out
         st = (B.ViewStats * n)() if stats else None
         o = self._opts(tile_size, bin_factor, tile_cap, st)
         pc = B.poses_to_c(poses)
@@ -177,15 +199,19 @@ class Context:
                 "hab_render")
 
     def make_views(self, items):
-        """items: iterable of (scene, sensor, pose, rgb, depth, tri) with
-        tensors or None.  Returns a ctypes View array (keeps sensors alive)."""
+        """items: iterable of (scene, sensor, pose, rgb, depth, tri[, semantic])
+        with tensors or None.  Returns a ctypes View array (keeps sensors
+        alive)."""
         items = list(items)
         arr = (B.View * len(items))()
         keep = []
-        for k, (scene, sensor, pose, rgb, depth, tri) in enumerate(items):
+        for k, it in enumerate(items):
+            scene, sensor, pose, rgb, depth, tri = it[:6]
+            sem = it[6] if len(it) > 6 else None
             check_output("rgb", rgb, 1, sensor)
             check_output("depth", depth, 1, sensor)
             check_output("tri", tri, 1, sensor)
+            check_output("semantic", sem, 1, sensor)
             keep.append(sensor)
             arr[k].scene = scene.ptr
             arr[k].sensor = C.pointer(sensor)
@@ -193,6 +219,7 @@ class Context:
             arr[k].out_rgb = None if rgb is None else int(rgb.data_ptr())
             arr[k].out_depth = None if depth is None else int(depth.data_ptr())
             arr[k].out_tri = None if tri is None else int(tri.data_ptr())
+            arr[k].out_semantic = None if sem is None else int(sem.data_ptr())
         arr._keep = keep
         return arr
 
@@ -283,10 +310,11 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, scene, sensor, pose, rgb=None, depth=None, tri=None) -> int:
+    def submit(self, scene, sensor, pose, rgb=None, depth=None, tri=None, semantic=None) -> int:
         check_output("rgb", rgb, 1, sensor)
         check_output("depth", depth, 1, sensor)
         check_output("tri", tri, 1, sensor)
+        check_output("semantic", semantic, 1, sensor)
         v = B.View()
         v.scene = scene.ptr
         v.sensor = C.pointer(sensor)
@@ -294,9 +322,10 @@ class Server:
         v.out_rgb = None if rgb is None else int(rgb.data_ptr())
         v.out_depth = None if depth is None else int(depth.data_ptr())
         v.out_tri = None if tri is None else int(tri.data_ptr())
+        v.out_semantic = None if semantic is None else int(semantic.data_ptr())
         t = C.c_uint64()
         B.check(self.lib.hab_server_submit(self.h, C.byref(v), C.byref(t)), "hab_server_submit")
-        self._keep[t.value] = (rgb, depth, tri)
+        self._keep[t.value] = (rgb, depth, tri, semantic)
         return t.value
 
     @staticmethod

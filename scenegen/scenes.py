@@ -50,6 +50,9 @@ class Scene:
     free_discs: np.ndarray         # float64 [Nr, 3] (cx, cz, r) kept free of boxes
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # uint32 [T] object instance per triangle: one per structural surface
+    # (floor, ceiling, wall piece), one per furniture box (its five faces)
+    instances: np.ndarray | None = None
 
     @property
     def num_triangles(self) -> int:
@@ -158,6 +161,17 @@ def _box_rects(x0, x1, y0, y1, z0, z1, n=0):
     ]
 
 
+def _instances(rects, cell, num_boxes):
+    """Instance id per triangle.  The rects end with the five faces of each
+    box in placement order; every rect before them is a structural surface
+    with an id of its own, and a box's faces share one id."""
+    nu, nv = _counts(rects, cell)
+    nstruct = len(rects) - 5 * num_boxes
+    k = np.arange(len(rects), dtype=np.int64)
+    rect_inst = np.where(k < nstruct, k, nstruct + (k - nstruct) // 5)
+    return np.repeat(rect_inst, 2 * nu * nv).astype(np.uint32)
+
+
 def _finish(rects, cell, seed, walls, boxes, bounds, discs, name, meta):
     rng_c = np.random.Generator(np.random.PCG64([seed, 7]))
     pos, col, idx = _tessellate(rects, cell, rng_c)
@@ -165,7 +179,8 @@ def _finish(rects, cell, seed, walls, boxes, bounds, discs, name, meta):
                  np.asarray(walls, np.float64).reshape(-1, 4),
                  np.asarray(boxes, np.float64).reshape(-1, 4),
                  np.asarray(bounds, np.float64),
-                 np.asarray(discs, np.float64).reshape(-1, 3), name, meta)
+                 np.asarray(discs, np.float64).reshape(-1, 3), name, meta,
+                 _instances(rects, cell, len(boxes)))
 
 
 def make_room(seed: int, num_boxes: int = 20) -> Scene:

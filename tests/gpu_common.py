@@ -28,10 +28,10 @@ def gpu_ctx():
 
 def to_np(out):
     res = {}
-    for k in ("rgb", "depth", "tri"):
+    for k in ("rgb", "depth", "tri", "semantic"):
         if k in out and out[k] is not None:
             a = out[k].cpu().numpy()
-            if k == "tri":
+            if k in ("tri", "semantic"):
                 a = a.view(np.uint32)
             res[k] = a
     return res
@@ -43,6 +43,9 @@ def compare(g, o, what=""):
     if "tri" in g:
         bad = g["tri"] != o["tri"]
         assert not bad.any(), f"{what}: {int(bad.sum())} triangle ids differ, first at {np.argwhere(bad)[:3].tolist()}"
+    if "semantic" in g:
+        bad = g["semantic"] != o["semantic"]
+        assert not bad.any(), f"{what}: {int(bad.sum())} instance ids differ, first at {np.argwhere(bad)[:3].tolist()}"
     if "depth" in g:
         od = o["depth"].astype(np.float64)
         gd = g["depth"].astype(np.float64)
@@ -81,7 +84,8 @@ def oracle_compare_many(jobs, threads=None):
     def one(job):
         sc, sn, pose, g, st, what = job
         o = oracle.render_view(sc.positions, sc.colors, sc.indices, sn.width, sn.height, pose,
-                               hfov_deg=sn.hfov_deg, near_m=sn.near_m)
+                               hfov_deg=sn.hfov_deg, near_m=sn.near_m,
+                               instances=sc.instances if "semantic" in g else None)
         compare(g, o, what)
         if st is not None:
             for k in ("survivors", "bbox_tests", "covered"):

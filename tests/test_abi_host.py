@@ -55,11 +55,18 @@ def test_sensor_spec_paper_defaults(lib):
 
 
 @pytest.mark.parametrize("args", [(0, 16), (16, 0), (4097, 16), (16, 16, 0.0), (16, 16, 180.0),
-                                  (16, 16, 90.0, -1.0), (16, 16, 90.0, 0.0, 8),
+                                  (16, 16, 90.0, -1.0), (16, 16, 90.0, 0.0, 16),
                                   (16, 16, float("nan"))])
 def test_sensor_spec_rejects(lib, args):
     rc, _ = spec(*args)
     assert rc == B.HAB_ERR_INVALID_ARG
+
+
+def test_sensor_spec_semantic(lib):
+    """The semantic output bit (8) is accepted alone or with the others."""
+    for outputs in (B.OUT_SEMANTIC, B.OUT_RGB | B.OUT_DEPTH | B.OUT_SEMANTIC, 15):
+        rc, s = spec(64, 48, 90.0, 0.01, outputs)
+        assert rc == B.HAB_OK and s.outputs == outputs
 
 
 def test_null_arguments(lib):
