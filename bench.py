@@ -316,29 +316,39 @@ def main():
     p50, p99 = float(np.percentile(lat_ms, 50)), float(np.percentile(lat_ms, 99))
     log(f"step latency p50 {p50:.3f} ms, p99 {p99:.3f} ms")
 
-    # ---------------------------------------------------- + semantic attachment
-    # the same batch with the semantic instance mask written beside RGB+D
-    sensor_sem = ctx.sensor(256, 256, 90.0, 0.01, P.OUT_RGB | P.OUT_DEPTH | P.OUT_SEMANTIC)
+    # ---------------------------------------------------- sensor variants
+    # the same batch with the semantic instance mask written beside RGB+D,
+    # and with noisy depth (sigma 0.1 / m, a fresh seed per view and step)
+    def variant_fps(sn, sem=None, noisy=False):
+        items_v = [(hs[w.env_scene[e]], sn, w.poses[0, e], rgb[e], depth[e], None,
+                    None if sem is None else sem[e], e) for e in range(E)]
+        views_v = ctx.make_views(items_v)
+        if not a.tile_size:
+            ctx.autotune(items_v)      # its own batch class (the output mix is part of the key)
+
+        def step_v(step):
+            p = w.poses[step % w.num_steps]
+            for e in range(E):
+                views_v[e].pose = B.pose_to_c(p[e])
+                if noisy:
+                    views_v[e].noise_seed = (step << 16) | e
+            ctx.render_batch(None, views=views_v, tile_size=a.tile_size)
+
+        for s in range(a.warmup):
+            step_v(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(a.steps):
+            step_v(s)
+        torch.cuda.synchronize()
+        return E * a.steps / (time.perf_counter() - t0)
+
     sem = torch.empty((E, 256, 256), dtype=torch.int32, device="cuda")
-    views_sem = ctx.make_views([(hs[w.env_scene[e]], sensor_sem, w.poses[0, e], rgb[e], depth[e],
-                                 None, sem[e]) for e in range(E)])
-
-    def sem_step(step):
-        p = w.poses[step % w.num_steps]
-        for e in range(E):
-            views_sem[e].pose = B.pose_to_c(p[e])
-        ctx.render_batch(None, views=views_sem, tile_size=a.tile_size)
-
-    for s in range(a.warmup):
-        sem_step(s)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(a.steps):
-        sem_step(s)
-    torch.cuda.synchronize()
-    fps_sem = E * a.steps / (time.perf_counter() - t0)
+    fps_sem = variant_fps(ctx.sensor(256, 256, 90.0, 0.01, P.OUT_RGB | P.OUT_DEPTH | P.OUT_SEMANTIC), sem)
     del sem
     log(f"batched eager, RGB + depth + semantic: {fps_sem:.0f} frames/s")
+    fps_noisy = variant_fps(ctx.sensor(256, 256, depth_noise_sigma=0.1), noisy=True)
+    log(f"batched eager, RGB + noisy depth: {fps_noisy:.0f} frames/s")
 
     # ---------------------------------------------------- work counters
     # the same poses as the timed steps, rendered again with counters on
@@ -450,6 +460,7 @@ def main():
         "batched_fps": round(fps_batch, 1),
         "batched_graph_fps": round(fps_graph, 1),
         "batched_rgbd_semantic_fps": round(fps_sem, 1),
+        "batched_rgb_noisy_depth_fps": round(fps_noisy, 1),
         "per_view_fps": round(fps_pv, 1),
         "batched_over_per_view": round(fps_batch / fps_pv, 2),
         "p50_step_ms": round(p50, 4),

@@ -97,12 +97,23 @@ typedef struct {
 
 /* Sensor request.  width, height in [1, 4096]; hfov_deg in (0, 180);
  * near_m > 0 (0 selects the default 0.01 m); outputs = OR of HAB_OUT_*
- * (0 selects RGB | DEPTH). */
+ * (0 selects RGB | DEPTH).
+ *
+ * depth_noise_sigma (1/m, finite, >= 0; 0 = the ideal depth sensor): the
+ * noisy depth of the appendix's noise study ("Noisy Depth"): iid Gaussian
+ * noise of standard deviation sigma added to each pixel's inverse depth,
+ * rho' = rho + sigma n; the depth output is 1/rho' where rho' > 0 and 0
+ * where rho' <= 0 or nothing is visible.  n is drawn per pixel from
+ * Philox4x64-10 (Salmon et al., SC 2011) with key (view noise seed,
+ * 0x6465707468) and counter (j W + i, 0, 0, 0): u1 = ((x0 >> 40) + 1) 2^-24,
+ * u2 = (x1 >> 40) 2^-24, n = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller),
+ * evaluated in fp32.  The seed comes with each view (hab_view.noise_seed). */
 typedef struct {
     uint32_t width, height;
     float hfov_deg;
     float near_m;
     uint32_t outputs;
+    float depth_noise_sigma;
 } hab_sensor_desc;
 
 /* Validated sensor (plain data, filled by hab_sensor_spec). */
@@ -111,6 +122,7 @@ typedef struct {
     float hfov_deg;
     float f;       /* focal length in px, fp32 */
     float near_m;
+    float depth_noise_sigma;
 } hab_sensor;
 
 /* Camera pose: world_from_camera.  position in metres, rotation row-major,
@@ -146,7 +158,9 @@ typedef struct {
  * (device pointers sized for that sensor; NULL for unwanted outputs).
  * out_semantic ([H][W] uint32, HAB_NO_HIT where nothing is visible) is
  * written when the sensor has HAB_OUT_SEMANTIC; the scene must then have an
- * instance table (else HAB_ERR_INVALID_ARG). */
+ * instance table (else HAB_ERR_INVALID_ARG).  noise_seed keys the depth
+ * noise of a sensor with depth_noise_sigma > 0 (the same seed and pose give
+ * the same noise; vary it per frame for fresh noise). */
 typedef struct {
     const hab_scene *scene;
     const hab_sensor *sensor;
@@ -155,6 +169,7 @@ typedef struct {
     float *out_depth;
     uint32_t *out_tri;
     uint32_t *out_semantic;
+    uint64_t noise_seed;
 } hab_view;
 
 /* ---------------------------------------------------------- lifetime */
@@ -196,7 +211,8 @@ hab_status hab_render(hab_context *ctx, const hab_scene *scene, const hab_sensor
  * uint32 or NULL) and options (NULL = defaults).  With opts->stats set
  * the call synchronises the stream before returning.  hab_render and
  * hab_render_ex have no semantic output: they ignore HAB_OUT_SEMANTIC
- * (hab_view carries it, for hab_render_batch, the stepper and the server). */
+ * (hab_view carries it, for hab_render_batch, the stepper and the server).
+ * Their depth noise seed is the pose index k. */
 hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
                          const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb,
                          float *out_depth, uint32_t *out_tri, const hab_render_opts *opts,
@@ -211,7 +227,8 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t nu
 /* A fixed batch composition captured once as a HIP graph.  Each step
  * takes new poses (host array [num_views]), validates them, stages them
  * in pinned memory and replays the graph on the stream.  The views'
- * output pointers are those given at creation. */
+ * output pointers are those given at creation.  Step s (counted from 0 at
+ * creation) renders view k with depth noise seed views[k].noise_seed + s. */
 hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t num_views,
                               const hab_render_opts *opts, hipStream_t stream,
                               hab_stepper **out);

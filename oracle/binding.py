@@ -73,6 +73,15 @@ def _load():
             lib.or_project_point.restype = C.c_int
             lib.or_project_point.argtypes = [f32p, f32p, C.c_uint32, C.c_uint32, C.c_double,
                                              C.c_float, i64p, i64p, f32p]
+            u64p = C.POINTER(C.c_uint64)
+            f64p = C.POINTER(C.c_double)
+            lib.or_philox4x64_10.restype = None
+            lib.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
+            lib.or_depth_noise_normal.restype = C.c_double
+            lib.or_depth_noise_normal.argtypes = [C.c_uint64, C.c_uint64]
+            lib.or_depth_noise.restype = C.c_int
+            lib.or_depth_noise.argtypes = [f32p, u32p, C.c_uint32, C.c_uint32, C.c_double,
+                                           C.c_uint64, f64p, f64p]
             _lib = lib
     return _lib
 
@@ -119,17 +128,49 @@ def semantic_image(tri, instances):
     return out
 
 
+def philox4x64_10(counter, key):
+    """Philox4x64-10 block: four 64-bit words for a 4-word counter and a
+    2-word key."""
+    c = np.ascontiguousarray(counter, np.uint64).reshape(4)
+    k = np.ascontiguousarray(key, np.uint64).reshape(2)
+    out = np.empty(4, np.uint64)
+    _load().or_philox4x64_10(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(out, C.c_uint64))
+    return out
+
+
+def depth_noise_normal(seed, pixel) -> float:
+    """The standard normal deviate of one pixel of a view with this seed."""
+    return float(_load().or_depth_noise_normal(int(seed), int(pixel)))
+
+
+def depth_noise(rho, tri, sigma, seed):
+    """Noisy inverse depth and depth (fp64 [H, W]) from a render's raw key
+    rho and visible triangle."""
+    rho = np.ascontiguousarray(rho, np.float32)
+    tri = np.ascontiguousarray(tri, np.uint32)
+    H, W = rho.shape
+    rp = np.empty((H, W), np.float64)
+    dp = np.empty((H, W), np.float64)
+    rc = _load().or_depth_noise(_ptr(rho, C.c_float), _ptr(tri, C.c_uint32), W, H, float(sigma),
+                                int(seed), _ptr(rp, C.c_double), _ptr(dp, C.c_double))
+    if rc != OR_OK:
+        raise OracleError(rc)
+    return rp, dp
+
+
 def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.01,
-                raw=False, instances=None):
+                raw=False, instances=None, noise_sigma=0.0, noise_seed=0):
     """Render one view.  Returns dict(rgb [H,W,3] u8, depth [H,W] f32,
     tri [H,W] u32, stats), with ``instances`` ([T] u32 per-triangle ids) also
-    semantic [H,W] u32, and with ``raw`` rho [H,W] f32 and key [H,W] u32.
-    Raises on a non-OK status."""
+    semantic [H,W] u32, with ``noise_sigma`` > 0 also the noisy inverse depth
+    and depth (rho_noisy, depth_noisy: [H,W] f64), and with ``raw`` rho
+    [H,W] f32 and key [H,W] u32.  Raises on a non-OK status."""
     pos, col, idx = _geom(positions, colors, indices)
     pose = np.ascontiguousarray(pose, np.float32).reshape(12)
     rgb = np.empty((H, W, 3), np.uint8)
     depth = np.empty((H, W), np.float32)
     tri = np.empty((H, W), np.uint32)
+    raw = raw or noise_sigma > 0.0
     rho = np.empty((H, W), np.float32) if raw else None
     key = np.empty((H, W), np.uint32) if raw else None
     st = Stats()
@@ -143,6 +184,8 @@ def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.
     out = {"rgb": rgb, "depth": depth, "tri": tri, "stats": st.as_dict()}
     if instances is not None:
         out["semantic"] = semantic_image(tri, instances)
+    if noise_sigma > 0.0:
+        out["rho_noisy"], out["depth_noisy"] = depth_noise(rho, tri, noise_sigma, noise_seed)
     if raw:
         out["rho"] = rho
         out["key"] = key

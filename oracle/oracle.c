@@ -430,3 +430,86 @@ int or_project_point(const float *P, const float *pose, uint32_t W, uint32_t H,
     *rw = s.rw;
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Noisy depth (the appendix's noise study, "Noisy Depth"): iid Gaussian
+ * noise of mean 0 and standard deviation sigma added to each pixel's
+ * inverse depth, so the error in depth grows with depth.  The paper states
+ * no generator and gives two inconsistent sigma values; the reading taken
+ * here: sigma is a sensor parameter in 1/m, the noisy inverse depth is
+ * rho' = rho + sigma * n, the noisy depth is 1/rho' when rho' > 0 and 0
+ * (no return) otherwise, and pixels with nothing visible stay 0.
+ *
+ * n comes from a counter-based generator so that any pixel's noise can be
+ * drawn on its own: Philox4x64 with 10 rounds (Salmon, Moraes, Dror and
+ * Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC 2011), keyed by
+ * (view seed, depth-noise stream tag), counter (pixel index j*W + i, 0, 0,
+ * 0).  Of its four 64-bit words, the top 24 bits of word 0 and of word 1
+ * give u1 = (a + 1) / 2^24 in (0, 1] and u2 = b / 2^24 in [0, 1), and the
+ * Box-Muller transform (1958) gives n = sqrt(-2 ln u1) cos(2 pi u2).  The
+ * oracle evaluates n and rho' in fp64.
+ * ---------------------------------------------------------------------- */
+#define OR_PHILOX_M0 0xD2E7470EE14C6C93ull
+#define OR_PHILOX_M1 0xCA5A826395121157ull
+#define OR_PHILOX_W0 0x9E3779B97F4A7C15ull /* golden ratio */
+#define OR_PHILOX_W1 0xBB67AE8584CAA73Bull /* sqrt(3) - 1 */
+#define OR_DEPTH_NOISE_TAG 0x6465707468ull  /* "depth" */
+
+void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += OR_PHILOX_W0;
+            k1 += OR_PHILOX_W1;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)OR_PHILOX_M0 * c0;
+        const unsigned __int128 p1 = (unsigned __int128)OR_PHILOX_M1 * c2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* The standard normal deviate of one pixel (fp64). */
+double or_depth_noise_normal(uint64_t seed, uint64_t pixel)
+{
+    const uint64_t ctr[4] = {pixel, 0, 0, 0};
+    const uint64_t key[2] = {seed, OR_DEPTH_NOISE_TAG};
+    uint64_t x[4];
+    or_philox4x64_10(ctr, key, x);
+    const double u1 = (double)((x[0] >> 40) + 1) / 16777216.0;
+    const double u2 = (double)(x[1] >> 40) / 16777216.0;
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+}
+
+/* Noisy inverse depth and depth of a W x H view from its per-pixel key rho
+ * (fp32, as the render's raw output) and visible triangle (OR_NONE: none).
+ * rho_out / depth_out: fp64 [H][W]; nothing visible gives 0 in both. */
+int or_depth_noise(const float *rho, const uint32_t *tri, uint32_t W, uint32_t H, double sigma,
+                   uint64_t seed, double *rho_out, double *depth_out)
+{
+    if (!rho || !tri || !rho_out || !depth_out || !(sigma >= 0.0)) return OR_ERR_INVALID_ARG;
+    for (uint32_t j = 0; j < H; ++j)
+        for (uint32_t i = 0; i < W; ++i) {
+            const size_t p = (size_t)j * W + i;
+            if (tri[p] == OR_NONE) {
+                rho_out[p] = 0.0;
+                depth_out[p] = 0.0;
+                continue;
+            }
+            const double rp = (double)rho[p] + sigma * or_depth_noise_normal(seed, (uint64_t)p);
+            rho_out[p] = rp;
+            depth_out[p] = rp > 0.0 ? 1.0 / rp : 0.0;
+        }
+    return OR_OK;
+}

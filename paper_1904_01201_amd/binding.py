@@ -47,12 +47,13 @@ class MeshDesc(C.Structure):
 
 class SensorDesc(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("hfov_deg", C.c_float),
-                ("near_m", C.c_float), ("outputs", C.c_uint32)]
+                ("near_m", C.c_float), ("outputs", C.c_uint32), ("depth_noise_sigma", C.c_float)]
 
 
 class Sensor(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("outputs", C.c_uint32),
-                ("hfov_deg", C.c_float), ("f", C.c_float), ("near_m", C.c_float)]
+                ("hfov_deg", C.c_float), ("f", C.c_float), ("near_m", C.c_float),
+                ("depth_noise_sigma", C.c_float)]
 
 
 class Pose(C.Structure):
@@ -71,7 +72,7 @@ class RenderOpts(C.Structure):
 class View(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("sensor", C.POINTER(Sensor)), ("pose", Pose),
                 ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_tri", C.c_void_p),
-                ("out_semantic", C.c_void_p)]
+                ("out_semantic", C.c_void_p), ("noise_seed", C.c_uint64)]
 
 
 class ServerCfg(C.Structure):

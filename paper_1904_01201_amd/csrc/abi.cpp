@@ -266,6 +266,7 @@ hab_status hab_sensor_spec(const hab_sensor_desc *d, hab_sensor *out)
     const uint32_t outputs = d->outputs ? d->outputs : (HAB_OUT_RGB | HAB_OUT_DEPTH);
     if (outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI | HAB_OUT_SEMANTIC))
         return HAB_ERR_INVALID_ARG;
+    if (!(d->depth_noise_sigma >= 0.0f) || !std::isfinite(d->depth_noise_sigma)) return HAB_ERR_INVALID_ARG;
     hab_sensor s;
     s.width = d->width;
     s.height = d->height;
@@ -273,6 +274,7 @@ hab_status hab_sensor_spec(const hab_sensor_desc *d, hab_sensor *out)
     s.hfov_deg = d->hfov_deg;
     s.f = (float)((double)d->width / (2.0 * std::tan((double)d->hfov_deg * 3.14159265358979323846 / 360.0)));
     s.near_m = near_m;
+    s.depth_noise_sigma = d->depth_noise_sigma;
     if (!(s.f > 0.0f) || !std::isfinite(s.f)) return HAB_ERR_INVALID_ARG;
     *out = s;
     return HAB_OK;
@@ -302,6 +304,7 @@ static hab_status render_common(hab_context *ctx, const hab_scene *scene, const 
             r.rgb = (rgb && (sensor->outputs & HAB_OUT_RGB)) ? rgb + 3 * px * k : nullptr;
             r.depth = (depth && (sensor->outputs & HAB_OUT_DEPTH)) ? depth + px * k : nullptr;
             r.tri = tri ? tri + px * k : nullptr;
+            r.noise_seed = k;
         }
         PlanOpts o;
         if (opts) {

@@ -44,7 +44,9 @@ struct alignas(16) DView {
     uint32_t pad;
     const uint32_t *inst;       // [T] instance id per triangle (semantic output)
     uint32_t *sem;              // [H][W] or null
-    uint32_t pad2[4];
+    float noise_sigma;          // depth noise in 1/m (0: ideal depth)
+    uint32_t pad2;
+    uint64_t noise_seed;        // key of the per-pixel depth noise
 };
 static_assert(sizeof(DView) == 224, "DView layout");
 

@@ -1153,6 +1153,38 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     if (rerr) atomicOr(err, kErrRange);
 }
 
+// Depth noise (the appendix's noise study): a standard normal deviate per
+// pixel, added to the inverse depth times the sensor's sigma.  Philox4x64
+// with 10 rounds (Salmon, Moraes, Dror and Shaw, SC 2011) keyed by (view
+// seed, stream tag), counter (pixel index, 0, 0, 0), so each pixel draws on
+// its own, whatever thread renders it; the top 24 bits of the first two
+// words feed the Box-Muller transform.
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;   // Weyl key increments
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+constexpr uint64_t kDepthNoiseTag = 0x6465707468ull;    // "depth"
+
+__device__ __forceinline__ float depth_noise_normal(uint64_t seed, uint64_t pixel)
+{
+    uint64_t c0 = pixel, c1 = 0, c2 = 0, c3 = 0;
+    uint64_t k0 = seed, k1 = kDepthNoiseTag;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+        const uint64_t hi1 = __umul64hi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    const float u1 = (float)((uint32_t)(c0 >> 40) + 1u) * 0x1p-24f;   // (0, 1]
+    const float u2 = (float)(uint32_t)(c1 >> 40) * 0x1p-24f;          // [0, 1)
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
 // Per tile: merge the segments' winners (largest 1/w, smaller key on a
 // tie: the same order-free rule), then shade and write the outputs.
 template <int TS>
@@ -1199,6 +1231,10 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
     float depth = 0.0f;
     if (best_key != kNone && !resolve(v, best_key, pi, pj, rgb, depth)) atomicOr(err, kErrResolve);
     const size_t p = (size_t)pj * v.W + (size_t)pi;
+    if (v.noise_sigma > 0.0f && best_key != kNone) {
+        const float rp = best_rho + v.noise_sigma * depth_noise_normal(v.noise_seed, (uint64_t)p);
+        depth = rp > 0.0f ? 1.0f / rp : 0.0f;
+    }
     if (v.rgb) {
         auto *o = gmem_out(v.rgb) + 3 * p;
         o[0] = (uint8_t)rgb[0];

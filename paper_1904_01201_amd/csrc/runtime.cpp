@@ -96,6 +96,7 @@ hab_status validate_sensor(const hab_sensor *s)
         (s->outputs & ~(uint32_t)(HAB_OUT_RGB | HAB_OUT_DEPTH | HAB_OUT_TRI | HAB_OUT_SEMANTIC)))
         return HAB_ERR_INVALID_ARG;
     if (s->f != (float)focal_of(s->width, s->hfov_deg)) return HAB_ERR_INVALID_ARG;
+    if (!(s->depth_noise_sigma >= 0.0f) || !std::isfinite(s->depth_noise_sigma)) return HAB_ERR_INVALID_ARG;
     return HAB_OK;
 }
 
@@ -148,6 +149,7 @@ hab_status to_view_req(const hab_view &hv, ViewReq &out)
     out.depth = (hv.sensor->outputs & HAB_OUT_DEPTH) ? hv.out_depth : nullptr;
     out.tri = hv.out_tri;
     out.sem = (hv.sensor->outputs & HAB_OUT_SEMANTIC) ? hv.out_semantic : nullptr;
+    out.noise_seed = hv.noise_seed;
     if (out.sem && !sc->inst) return HAB_ERR_INVALID_ARG;
     return HAB_OK;
 }
@@ -222,6 +224,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.tri = r.tri;
         d.inst = r.scene->inst;
         d.sem = r.sem;
+        d.noise_sigma = r.sensor.depth_noise_sigma;
+        d.noise_seed = r.noise_seed;
         d.tiles_x = cdiv(d.W, ts);
         d.tiles_y = cdiv(d.H, ts);
         d.tile_base = (uint32_t)tile_total;

@@ -40,6 +40,7 @@ struct ViewReq {
     float *depth;
     uint32_t *tri;
     uint32_t *sem;
+    uint64_t noise_seed;
 };
 
 struct PlanOpts {

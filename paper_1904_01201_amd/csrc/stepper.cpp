@@ -28,6 +28,7 @@ struct hab_stepper {
     hipStream_t last_stream = nullptr;
     hipStream_t cap = nullptr;
     int next = 0;
+    uint64_t steps = 0;         // steps taken (advances the depth noise seeds)
 };
 
 static void destroy(hab_stepper *st)
@@ -145,12 +146,14 @@ hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t 
             const hab_pose &p = poses[st->plan.order[k]];
             std::memcpy(d->p, p.position, sizeof d->p);
             std::memcpy(d->R, p.rotation, sizeof d->R);
+            d->noise_seed = st->req[st->plan.order[k]].noise_seed + st->steps;
         }
         if (st->has_last && st->last_stream != stream &&
             hipStreamWaitEvent(stream, st->last, 0) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
         if (hipGraphLaunch(st->exec[b], stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
         if (hipEventRecord(st->ev[b], stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
         st->pending[b] = true;
+        ++st->steps;
         if (hipEventRecord(st->last, stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
         st->has_last = true;
         st->last_stream = stream;

@@ -117,9 +117,12 @@ class Context:
 
     # ------------------------------------------------------------ sensors
     @staticmethod
-    def sensor(width, height, hfov_deg=90.0, near_m=0.01, outputs=B.OUT_RGB | B.OUT_DEPTH) -> B.Sensor:
+    def sensor(width, height, hfov_deg=90.0, near_m=0.01, outputs=B.OUT_RGB | B.OUT_DEPTH,
+               depth_noise_sigma=0.0) -> B.Sensor:
+        """depth_noise_sigma: iid Gaussian noise on the inverse depth, in 1/m."""
         lib = B.load()
-        d = B.SensorDesc(int(width), int(height), float(hfov_deg), float(near_m), int(outputs))
+        d = B.SensorDesc(int(width), int(height), float(hfov_deg), float(near_m), int(outputs),
+                         float(depth_noise_sigma))
         s = B.Sensor()
         B.check(lib.hab_sensor_spec(C.byref(d), C.byref(s)), "hab_sensor_spec")
         return s
@@ -152,8 +155,9 @@ class Context:
                tile_size=0, bin_factor=0.0, tile_cap=0, stats=False, stream=None, out=None):
         """Render N views of one scene.  Returns dict of output tensors (and
         'stats': list of dicts if requested).  A sensor with the semantic
-        output goes through hab_render_batch (one view per pose), since
-        hab_render_ex has no semantic output."""
+        output goes through hab_render_batch (one view per pose, noise seed =
+        pose index as in hab_render_ex), since hab_render_ex has no semantic
+        output."""
         poses = np.asarray(poses, np.float32).reshape(-1, 12)
         n = poses.shape[0]
         if out is None:
@@ -170,7 +174,7 @@ class Context:
             check_output(k, out.get(k), n, sensor)
         if out.get("semantic") is not None:
             items = [(scene, sensor, poses[k], *[None if out.get(name) is None else out[name][k]
-                                                 for name in ("rgb", "depth", "tri", "semantic")])
+                                                 for name in ("rgb", "depth", "tri", "semantic")], k)
                      for k in range(n)]
             st = self.render_batch(items, tile_size, bin_factor, tile_cap, stats, stream)
             if stats:
@@ -199,15 +203,16 @@ class Context:
                 "hab_render")
 
     def make_views(self, items):
-        """items: iterable of (scene, sensor, pose, rgb, depth, tri[, semantic])
-        with tensors or None.  Returns a ctypes View array (keeps sensors
-        alive)."""
+        """items: iterable of (scene, sensor, pose, rgb, depth, tri[, semantic
+        [, noise_seed]]) with tensors or None.  Returns a ctypes View array
+        (keeps sensors alive)."""
         items = list(items)
         arr = (B.View * len(items))()
         keep = []
         for k, it in enumerate(items):
             scene, sensor, pose, rgb, depth, tri = it[:6]
             sem = it[6] if len(it) > 6 else None
+            seed = int(it[7]) if len(it) > 7 else 0
             check_output("rgb", rgb, 1, sensor)
             check_output("depth", depth, 1, sensor)
             check_output("tri", tri, 1, sensor)
@@ -220,6 +225,7 @@ class Context:
             arr[k].out_depth = None if depth is None else int(depth.data_ptr())
             arr[k].out_tri = None if tri is None else int(tri.data_ptr())
             arr[k].out_semantic = None if sem is None else int(sem.data_ptr())
+            arr[k].noise_seed = seed
         arr._keep = keep
         return arr
 
@@ -310,7 +316,8 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, scene, sensor, pose, rgb=None, depth=None, tri=None, semantic=None) -> int:
+    def submit(self, scene, sensor, pose, rgb=None, depth=None, tri=None, semantic=None,
+               noise_seed=0) -> int:
         check_output("rgb", rgb, 1, sensor)
         check_output("depth", depth, 1, sensor)
         check_output("tri", tri, 1, sensor)
@@ -323,6 +330,7 @@ class Server:
         v.out_depth = None if depth is None else int(depth.data_ptr())
         v.out_tri = None if tri is None else int(tri.data_ptr())
         v.out_semantic = None if semantic is None else int(semantic.data_ptr())
+        v.noise_seed = int(noise_seed)
         t = C.c_uint64()
         B.check(self.lib.hab_server_submit(self.h, C.byref(v), C.byref(t)), "hab_server_submit")
         self._keep[t.value] = (rgb, depth, tri, semantic)

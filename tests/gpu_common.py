@@ -61,6 +61,30 @@ def compare(g, o, what=""):
     return 0
 
 
+def compare_noisy_depth(gd, o, sigma, what=""):
+    """Noisy depth parity.  The GPU evaluates the Box-Muller deviate in
+    fp32 (logf, sqrtf, cospif: a few ulp each, |n| <= 5.8) and the oracle in
+    fp64 from the same 24-bit uniforms, so the inverse depths differ by at
+    most ~3e-6 sigma + 2e-7 rho; the bar is 1e-5 (rho + sigma) on
+    1/depth.  Where the oracle's noisy inverse depth lies within that band
+    of 0 the GPU may read either side (a return or none); elsewhere the
+    validity must agree.  Returns the number of band pixels."""
+    hit = o["tri"] != NONE
+    rho = o["rho"].astype(np.float64)
+    rp = o["rho_noisy"]
+    tol = 1e-5 * (rho + sigma)
+    gd = gd.astype(np.float64)
+    assert (gd[~hit] == 0).all(), f"{what}: noisy depth where nothing is visible"
+    sure_pos = hit & (rp > tol)
+    sure_neg = hit & (rp < -tol)
+    assert (gd[sure_pos] > 0).all(), f"{what}: {int((gd[sure_pos] <= 0).sum())} returns lost"
+    assert (gd[sure_neg] == 0).all(), f"{what}: {int((gd[sure_neg] != 0).sum())} spurious returns"
+    err = np.abs(1.0 / gd[sure_pos] - rp[sure_pos])
+    assert err.size == 0 or (err <= tol[sure_pos]).all(), \
+        f"{what}: inverse depth error {(err / tol[sure_pos]).max():.3g} x the bar"
+    return int((hit & ~sure_pos & ~sure_neg).sum())
+
+
 def check_any_size(out, T, what):
     """Properties of one view's outputs that need no oracle: ids in range,
     nothing written where nothing is visible, positive finite depth."""

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1904_01201_amd as P
@@ -40,8 +41,8 @@ def test_status_strings(lib):
     assert lib.hab_status_string(99) == b"unknown status"
 
 
-def spec(w, h, hfov=90.0, near=0.0, outputs=0):
-    d = B.SensorDesc(w, h, hfov, near, outputs)
+def spec(w, h, hfov=90.0, near=0.0, outputs=0, noise=0.0):
+    d = B.SensorDesc(w, h, hfov, near, outputs, noise)
     s = B.Sensor()
     rc = B.load().hab_sensor_spec(C.byref(d), C.byref(s))
     return rc, s
@@ -56,7 +57,9 @@ def test_sensor_spec_paper_defaults(lib):
 
 @pytest.mark.parametrize("args", [(0, 16), (16, 0), (4097, 16), (16, 16, 0.0), (16, 16, 180.0),
                                   (16, 16, 90.0, -1.0), (16, 16, 90.0, 0.0, 16),
-                                  (16, 16, float("nan"))])
+                                  (16, 16, float("nan")), (16, 16, 90.0, 0.0, 3, -0.1),
+                                  (16, 16, 90.0, 0.0, 3, float("nan")),
+                                  (16, 16, 90.0, 0.0, 3, float("inf"))])
 def test_sensor_spec_rejects(lib, args):
     rc, _ = spec(*args)
     assert rc == B.HAB_ERR_INVALID_ARG
@@ -67,6 +70,14 @@ def test_sensor_spec_semantic(lib):
     for outputs in (B.OUT_SEMANTIC, B.OUT_RGB | B.OUT_DEPTH | B.OUT_SEMANTIC, 15):
         rc, s = spec(64, 48, 90.0, 0.01, outputs)
         assert rc == B.HAB_OK and s.outputs == outputs
+
+
+def test_sensor_spec_depth_noise(lib):
+    """The noise sigma is carried through unchanged (0 = ideal depth)."""
+    rc, s = spec(64, 48, 90.0, 0.01, 3, 0.4)
+    assert rc == B.HAB_OK and s.depth_noise_sigma == np.float32(0.4)
+    rc, s = spec(64, 48)
+    assert rc == B.HAB_OK and s.depth_noise_sigma == 0.0
 
 
 def test_null_arguments(lib):
