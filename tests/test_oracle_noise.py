@@ -53,6 +53,26 @@ def test_pixel_deviates_are_standard_normal(oracle_lib):
     assert np.abs(n).max() > 3.5 and np.abs(n).max() <= np.sqrt(2 * np.log(2.0 ** 24)) + 1e-12
 
 
+def test_deviate_sign_follows_the_angle(oracle_lib):
+    """Box-Muller's angle is 2 pi u2, with u2 the top 24 bits of the
+    block's second word: a pixel's deviate is positive exactly when u2 lies
+    in [0, 1/4) or (3/4, 1).  u2 comes from numpy's generator here, so
+    this ties the oracle's deviate to the definition's bits and angle (a
+    different angle scale keeps the distribution but breaks this)."""
+    seed, tag = 77, 0x6465707468
+    checked = 0
+    for p in range(4000):
+        x = numpy_philox_block([p, 0, 0, 0], [seed, tag])
+        k = int(x[1]) >> 40
+        if k in (1 << 22, 3 << 22):
+            continue
+        u2 = k / 2.0 ** 24
+        n = oracle_lib.depth_noise_normal(seed, p)
+        assert (n > 0) == (u2 < 0.25 or u2 > 0.75), (p, u2, n)
+        checked += 1
+    assert checked > 3990
+
+
 def wall(z):
     """A fronto-parallel quad covering the whole 90-degree view at depth -z."""
     e = 2.0 * abs(z)
