@@ -66,6 +66,11 @@ def _load():
                                            C.c_uint32, C.c_uint32, C.c_double, C.c_float,
                                            f32p, u8p, f32p, u32p, f32p, u32p,
                                            C.POINTER(Stats)]
+            lib.or_render_view_tex.restype = C.c_int
+            lib.or_render_view_tex.argtypes = [f32p, C.c_uint32, u32p, C.c_uint32, f32p, u8p,
+                                               C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                               C.c_double, C.c_float, f32p, u8p, f32p, u32p,
+                                               f32p, u32p, C.POINTER(Stats)]
             lib.or_coverage_count.restype = C.c_int
             lib.or_coverage_count.argtypes = [f32p, C.c_uint32, u32p, C.c_uint32,
                                               C.c_uint32, C.c_uint32, C.c_double, C.c_float,
@@ -159,12 +164,15 @@ def depth_noise(rho, tri, sigma, seed):
 
 
 def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.01,
-                raw=False, instances=None, noise_sigma=0.0, noise_seed=0):
+                raw=False, instances=None, noise_sigma=0.0, noise_seed=0, uvs=None,
+                texture=None):
     """Render one view.  Returns dict(rgb [H,W,3] u8, depth [H,W] f32,
     tri [H,W] u32, stats), with ``instances`` ([T] u32 per-triangle ids) also
     semantic [H,W] u32, with ``noise_sigma`` > 0 also the noisy inverse depth
     and depth (rho_noisy, depth_noisy: [H,W] f64), and with ``raw`` rho
-    [H,W] f32 and key [H,W] u32.  Raises on a non-OK status."""
+    [H,W] f32 and key [H,W] u32.  With ``uvs`` ([V,2] f32) and ``texture``
+    ([th,tw,3] u8) the colour is the bilinear texture fetch.  Raises on a
+    non-OK status."""
     pos, col, idx = _geom(positions, colors, indices)
     pose = np.ascontiguousarray(pose, np.float32).reshape(12)
     rgb = np.empty((H, W, 3), np.uint8)
@@ -174,11 +182,23 @@ def render_view(positions, colors, indices, W, H, pose, hfov_deg=90.0, near_m=0.
     rho = np.empty((H, W), np.float32) if raw else None
     key = np.empty((H, W), np.uint32) if raw else None
     st = Stats()
-    rc = _load().or_render_view(_ptr(pos, C.c_float), pos.shape[0], _ptr(col, C.c_uint8),
-                                _ptr(idx, C.c_uint32), idx.shape[0], W, H, hfov_deg, near_m,
-                                _ptr(pose, C.c_float), _ptr(rgb, C.c_uint8),
-                                _ptr(depth, C.c_float), _ptr(tri, C.c_uint32),
-                                _ptr(rho, C.c_float), _ptr(key, C.c_uint32), C.byref(st))
+    if texture is not None:
+        uv = np.ascontiguousarray(uvs, np.float32).reshape(-1, 2)
+        tex = np.ascontiguousarray(texture, np.uint8)
+        if uv.shape[0] != pos.shape[0] or tex.ndim != 3 or tex.shape[2] != 3:
+            raise ValueError("uvs must be [V, 2] and texture [th, tw, 3]")
+        rc = _load().or_render_view_tex(_ptr(pos, C.c_float), pos.shape[0], _ptr(idx, C.c_uint32),
+                                        idx.shape[0], _ptr(uv, C.c_float), _ptr(tex, C.c_uint8),
+                                        tex.shape[1], tex.shape[0], W, H, hfov_deg, near_m,
+                                        _ptr(pose, C.c_float), _ptr(rgb, C.c_uint8),
+                                        _ptr(depth, C.c_float), _ptr(tri, C.c_uint32),
+                                        _ptr(rho, C.c_float), _ptr(key, C.c_uint32), C.byref(st))
+    else:
+        rc = _load().or_render_view(_ptr(pos, C.c_float), pos.shape[0], _ptr(col, C.c_uint8),
+                                    _ptr(idx, C.c_uint32), idx.shape[0], W, H, hfov_deg, near_m,
+                                    _ptr(pose, C.c_float), _ptr(rgb, C.c_uint8),
+                                    _ptr(depth, C.c_float), _ptr(tri, C.c_uint32),
+                                    _ptr(rho, C.c_float), _ptr(key, C.c_uint32), C.byref(st))
     if rc != OR_OK:
         raise OracleError(rc)
     out = {"rgb": rgb, "depth": depth, "tri": tri, "stats": st.as_dict()}

@@ -51,17 +51,21 @@ typedef struct {
     uint64_t clipped;    /* triangles that straddle the near plane            */
 } or_stats;
 
-/* camera-space vertex with colour (0..255 as float) */
+/* Vertex attributes carried through clipping and interpolation: colour
+ * (0..255 as float) in 0..2, texture coordinates (u, v) in 3..4. */
+#define OR_NA 5
+
+/* camera-space vertex with its attributes */
 typedef struct {
     float x, y, w;
-    float c[3];
+    float c[OR_NA];
 } cvert;
 
 /* snapped screen vertex */
 typedef struct {
     int64_t X, Y;
     float rw;
-    float c[3];
+    float c[OR_NA];
 } svert;
 
 /* ------------------------------------------------------------------ a1 */
@@ -150,7 +154,7 @@ static int clip_near(const cvert in[3], float zn, cvert out[4])
             cvert q;
             q.x = s->x + t * (o->x - s->x);
             q.y = s->y + t * (o->y - s->y);
-            for (int c = 0; c < 3; ++c) q.c[c] = s->c[c] + t * (o->c[c] - s->c[c]);
+            for (int c = 0; c < OR_NA; ++c) q.c[c] = s->c[c] + t * (o->c[c] - s->c[c]);
             q.w = zn;
             out[n++] = q;
         }
@@ -172,7 +176,7 @@ static int project(const cvert *v, float fS, float cxS, float cyS, svert *s)
     s->X = (int64_t)xs;
     s->Y = (int64_t)ys;
     s->rw = rw;
-    for (int c = 0; c < 3; ++c) s->c[c] = v->c[c];
+    for (int c = 0; c < OR_NA; ++c) s->c[c] = v->c[c];
     return OR_OK;
 }
 
@@ -205,7 +209,7 @@ typedef struct {
     uint32_t key;    /* 2 * triangle index + sub-triangle, OR_NONE = empty  */
     float wgt[3];    /* b_k * rw_k of the winner at this pixel              */
     float num;       /* (wgt0 + wgt1) + wgt2                                */
-    float col[3][3]; /* the winner's vertex colours                         */
+    float col[3][OR_NA]; /* the winner's vertex attributes                  */
 } zpix;
 
 typedef struct {
@@ -214,6 +218,9 @@ typedef struct {
     const uint8_t *col;
     const uint32_t *idx;
     uint32_t T;
+    const float *uv;      /* [V][2] texture coordinates, or NULL            */
+    const uint8_t *tex;   /* [th][tw][3] RGB texture, or NULL               */
+    uint32_t tw, th;
     uint32_t W, H;
     float fS, cxS, cyS, zn;
     const float *pose;
@@ -283,7 +290,7 @@ static void raster_tri(const view_in *in, svert v[3], uint32_t key, zpix *zb,
                 z->wgt[2] = w2;
                 z->num = num;
                 for (int k = 0; k < 3; ++k)
-                    for (int c = 0; c < 3; ++c) z->col[k][c] = v[k].c[c];
+                    for (int c = 0; c < OR_NA; ++c) z->col[k][c] = v[k].c[c];
             }
         }
     }
@@ -298,6 +305,8 @@ static int draw_view(const view_in *in, zpix *zb, uint32_t *count, or_stats *st)
             to_camera(in->pos + 3 * (size_t)vi, in->pose, &cv[k]);
             for (int c = 0; c < 3; ++c)
                 cv[k].c[c] = in->col ? (float)in->col[3 * (size_t)vi + c] : 255.0f;
+            cv[k].c[3] = in->uv ? in->uv[2 * (size_t)vi] : 0.0f;
+            cv[k].c[4] = in->uv ? in->uv[2 * (size_t)vi + 1] : 0.0f;
         }
         cvert poly[4];
         int n = clip_near(cv, in->zn, poly);
@@ -329,6 +338,9 @@ static int setup_view(view_in *in, const float *pos, uint32_t V, const uint8_t *
     in->col = col;
     in->idx = idx;
     in->T = T;
+    in->uv = NULL;
+    in->tex = NULL;
+    in->tw = in->th = 0;
     in->W = W;
     in->H = H;
     in->fS = or_focal(W, hfov_deg) * 256.0f;
@@ -338,6 +350,46 @@ static int setup_view(view_in *in, const float *pos, uint32_t V, const uint8_t *
     in->pose = pose;
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------ f2 */
+/* Textured shading.  Scanned scenes carry textures (Sec. 4 "Episode
+ * dataset preparation": textured meshes); the paper does not say how they
+ * are filtered, so the written definition is the classic one: texture
+ * coordinates interpolated perspective-correctly exactly as the colours
+ * are, then a bilinear fetch with the texel centres at ((k + 1/2) / tw,
+ * (l + 1/2) / th), v = 0 at the texture's first row, coordinates wrapping
+ * (repeat).  The texture size is a power of two and |u| tw, |v| th < 2^22
+ * at every vertex.  The fetch is evaluated in fp64 and rounded half to even
+ * into 0..255. */
+static uint32_t wrap(int64_t k, uint32_t n)
+{
+    int64_t m = k % (int64_t)n;
+    return (uint32_t)(m < 0 ? m + (int64_t)n : m);
+}
+
+static void tex_bilinear(const uint8_t *tex, uint32_t tw, uint32_t th, float u, float v,
+                         uint8_t out[3])
+{
+    const double x = (double)u * (double)tw - 0.5, y = (double)v * (double)th - 0.5;
+    const double xf = floor(x), yf = floor(y);
+    const double fx = x - xf, fy = y - yf;
+    const uint32_t i0 = wrap((int64_t)xf, tw), i1 = wrap((int64_t)xf + 1, tw);
+    const uint32_t j0 = wrap((int64_t)yf, th), j1 = wrap((int64_t)yf + 1, th);
+    for (int c = 0; c < 3; ++c) {
+        const double t00 = tex[((size_t)j0 * tw + i0) * 3 + c], t10 = tex[((size_t)j0 * tw + i1) * 3 + c];
+        const double t01 = tex[((size_t)j1 * tw + i0) * 3 + c], t11 = tex[((size_t)j1 * tw + i1) * 3 + c];
+        const double val = (1.0 - fy) * ((1.0 - fx) * t00 + fx * t10) + fy * ((1.0 - fx) * t01 + fx * t11);
+        double r = rint(val);
+        if (r < 0.0) r = 0.0;
+        if (r > 255.0) r = 255.0;
+        out[c] = (uint8_t)r;
+    }
+}
+
+static int pow2(uint32_t n) { return n != 0 && (n & (n - 1)) == 0; }
+
+static int render_core(view_in *in, uint8_t *rgb, float *depth, uint32_t *tri, float *rho_out,
+                       uint32_t *key_out, or_stats *st);
 
 /* Render one view.  Outputs (any may be NULL): rgb [H][W][3] uint8,
  * depth [H][W] float (planar metres, 0 = no hit), tri [H][W] uint32 (index
@@ -352,6 +404,38 @@ int or_render_view(const float *pos, uint32_t V, const uint8_t *col, const uint3
     view_in in;
     int rc = setup_view(&in, pos, V, col, idx, T, W, H, hfov_deg, near_m, pose);
     if (rc != OR_OK) return rc;
+    return render_core(&in, rgb, depth, tri, rho_out, key_out, st);
+}
+
+/* As or_render_view, with the colour taken from a texture: uv [V][2]
+ * float, tex [th][tw][3] uint8 (tw, th powers of two). */
+int or_render_view_tex(const float *pos, uint32_t V, const uint32_t *idx, uint32_t T,
+                       const float *uv, const uint8_t *tex, uint32_t tw, uint32_t th,
+                       uint32_t W, uint32_t H, double hfov_deg, float near_m, const float *pose,
+                       uint8_t *rgb, float *depth, uint32_t *tri, float *rho_out,
+                       uint32_t *key_out, or_stats *st)
+{
+    view_in in;
+    if (!uv || !tex || !pow2(tw) || !pow2(th) || tw > 16384 || th > 16384) return OR_ERR_INVALID_ARG;
+    for (size_t k = 0; k < V; ++k) {
+        const double a = fabs((double)uv[2 * k] * tw), b = fabs((double)uv[2 * k + 1] * th);
+        if (!(a < 4194304.0 && b < 4194304.0)) return OR_ERR_INVALID_ARG;
+    }
+    int rc = setup_view(&in, pos, V, NULL, idx, T, W, H, hfov_deg, near_m, pose);
+    if (rc != OR_OK) return rc;
+    in.uv = uv;
+    in.tex = tex;
+    in.tw = tw;
+    in.th = th;
+    return render_core(&in, rgb, depth, tri, rho_out, key_out, st);
+}
+
+static int render_core(view_in *in_, uint8_t *rgb, float *depth, uint32_t *tri, float *rho_out,
+                       uint32_t *key_out, or_stats *st)
+{
+    view_in in = *in_;
+    const uint32_t W = in.W, H = in.H;
+    int rc;
     or_stats local;
     memset(&local, 0, sizeof local);
     size_t np = (size_t)W * H;
@@ -374,7 +458,17 @@ int or_render_view(const float *pos, uint32_t V, const uint8_t *col, const uint3
         if (key_out) key_out[p] = z->key;
         if (tri) tri[p] = hit ? (z->key >> 1) : OR_NONE;
         if (depth) depth[p] = hit ? 1.0f / z->rho : 0.0f;
-        if (rgb) {
+        if (rgb && in.tex) {
+            uint8_t t[3] = {0, 0, 0};
+            if (hit) {
+                const float u = ((z->wgt[0] * z->col[0][3] + z->wgt[1] * z->col[1][3]) +
+                                 z->wgt[2] * z->col[2][3]) / z->num;
+                const float v = ((z->wgt[0] * z->col[0][4] + z->wgt[1] * z->col[1][4]) +
+                                 z->wgt[2] * z->col[2][4]) / z->num;
+                tex_bilinear(in.tex, in.tw, in.th, u, v, t);
+            }
+            for (int c = 0; c < 3; ++c) rgb[3 * p + c] = t[c];
+        } else if (rgb) {
             for (int c = 0; c < 3; ++c) {
                 uint8_t u = 0;
                 if (hit) {
