@@ -318,9 +318,11 @@ def main():
 
     # ---------------------------------------------------- sensor variants
     # the same batch with the semantic instance mask written beside RGB+D,
-    # and with noisy depth (sigma 0.1 / m, a fresh seed per view and step)
-    def variant_fps(sn, sem=None, noisy=False):
-        items_v = [(hs[w.env_scene[e]], sn, w.poses[0, e], rgb[e], depth[e], None,
+    # with noisy depth (sigma 0.1 / m, a fresh seed per view and step), and
+    # with the scenes textured (2048^2 RGB textures, 256 texels per metre)
+    def variant_fps(sn, sem=None, noisy=False, handles=None):
+        hv = hs if handles is None else handles
+        items_v = [(hv[w.env_scene[e]], sn, w.poses[0, e], rgb[e], depth[e], None,
                     None if sem is None else sem[e], e) for e in range(E)]
         views_v = ctx.make_views(items_v)
         if not a.tile_size:
@@ -349,6 +351,12 @@ def main():
     log(f"batched eager, RGB + depth + semantic: {fps_sem:.0f} frames/s")
     fps_noisy = variant_fps(ctx.sensor(256, 256, depth_noise_sigma=0.1), noisy=True)
     log(f"batched eager, RGB + noisy depth: {fps_noisy:.0f} frames/s")
+    from scenegen import with_texture
+    hs_tex = [ctx.upload_scene(with_texture(s)) for s in w.scenes]
+    fps_tex = variant_fps(sensor, handles=hs_tex)
+    for h in hs_tex:
+        ctx.release(h)
+    log(f"batched eager, textured RGB + depth: {fps_tex:.0f} frames/s")
 
     # ---------------------------------------------------- work counters
     # the same poses as the timed steps, rendered again with counters on
@@ -461,6 +469,7 @@ def main():
         "batched_graph_fps": round(fps_graph, 1),
         "batched_rgbd_semantic_fps": round(fps_sem, 1),
         "batched_rgb_noisy_depth_fps": round(fps_noisy, 1),
+        "batched_textured_rgbd_fps": round(fps_tex, 1),
         "per_view_fps": round(fps_pv, 1),
         "batched_over_per_view": round(fps_batch / fps_pv, 2),
         "p50_step_ms": round(p50, 4),

@@ -85,7 +85,18 @@ typedef struct hab_server hab_server;
  * [V][3] uint8 RGB (NULL: all white), indices [T][3] uint32 (each < V),
  * instances [T] uint32 instance id per triangle (NULL: the scene has no
  * semantic table and cannot feed HAB_OUT_SEMANTIC).  1 <= V < 2^30,
- * T < 2^30 (HAB_ERR_INVALID_ARG otherwise). */
+ * T < 2^30 (HAB_ERR_INVALID_ARG otherwise).
+ *
+ * Texture (scanned scenes are textured meshes, Sec. 4 "Episode dataset
+ * preparation"): uvs [V][2] float and texture [tex_height][tex_width][3]
+ * uint8 RGB, both or neither.  With a texture the colour output is the
+ * texture, not the vertex colours: texture coordinates are interpolated
+ * perspective-correctly like the colours (the same fp32 sequence, through
+ * the near clip), then fetched bilinearly with texel centres at
+ * ((k + 1/2) / tex_width, (l + 1/2) / tex_height), v = 0 at the first row,
+ * coordinates repeating.  tex_width and tex_height are powers of two in
+ * [1, 16384] and every vertex has |u| tex_width, |v| tex_height < 2^22
+ * (HAB_ERR_INVALID_ARG otherwise). */
 typedef struct {
     const float *positions;
     uint32_t num_vertices;
@@ -93,6 +104,9 @@ typedef struct {
     const uint32_t *indices;
     uint32_t num_triangles;
     const uint32_t *instances;
+    const float *uvs;
+    const uint8_t *texture;
+    uint32_t tex_width, tex_height;
 } hab_mesh_desc;
 
 /* Sensor request.  width, height in [1, 4096]; hfov_deg in (0, 180);

@@ -42,7 +42,8 @@ PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "
 class MeshDesc(C.Structure):
     _fields_ = [("positions", C.c_void_p), ("num_vertices", C.c_uint32),
                 ("colors", C.c_void_p), ("indices", C.c_void_p), ("num_triangles", C.c_uint32),
-                ("instances", C.c_void_p)]
+                ("instances", C.c_void_p), ("uvs", C.c_void_p), ("texture", C.c_void_p),
+                ("tex_width", C.c_uint32), ("tex_height", C.c_uint32)]
 
 
 class SensorDesc(C.Structure):

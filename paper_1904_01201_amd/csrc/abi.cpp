@@ -89,6 +89,18 @@ hab_status hab_init(int device, hab_context **out)
     });
 }
 
+// Device memory of a scene (every pointer may be null).
+static void free_scene_mem(Scene *s)
+{
+    (void)hipFree(s->pos);
+    (void)hipFree(s->col);
+    (void)hipFree(s->idx);
+    (void)hipFree(s->cbox);
+    (void)hipFree(s->inst);
+    (void)hipFree(s->uv);
+    (void)hipFree(s->tex);
+}
+
 hab_status hab_shutdown(hab_context *ctx)
 {
     if (!ctx) return HAB_ERR_INVALID_ARG;
@@ -96,11 +108,7 @@ hab_status hab_shutdown(hab_context *ctx)
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
         for (Scene *s : ctx->scenes) {
-            (void)hipFree(s->pos);
-            (void)hipFree(s->col);
-            (void)hipFree(s->idx);
-            (void)hipFree(s->cbox);
-            (void)hipFree(s->inst);
+            free_scene_mem(s);
             delete static_cast<hab_scene *>(s);
         }
         ctx->scenes.clear();
@@ -163,6 +171,24 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             cbox[2 * c] = make_float4(mn[0], mn[1], mn[2], 0.0f);
             cbox[2 * c + 1] = make_float4(mx[0], mx[1], mx[2], 0.0f);
         }
+        // texture: both parts or neither, power-of-two sizes, coordinates
+        // inside the range where u * tex_width keeps sub-texel precision
+        const bool textured = m->uvs || m->texture;
+        std::vector<uint32_t> texels;
+        if (textured) {
+            const uint32_t tw = m->tex_width, th = m->tex_height;
+            const bool pow2 = tw && th && !(tw & (tw - 1)) && !(th & (th - 1));
+            if (!m->uvs || !m->texture || !pow2 || tw > 16384 || th > 16384) return HAB_ERR_INVALID_ARG;
+            for (uint64_t k = 0; k < V; ++k) {
+                const double a = std::fabs((double)m->uvs[2 * k] * tw);
+                const double b = std::fabs((double)m->uvs[2 * k + 1] * th);
+                if (!(a < 4194304.0 && b < 4194304.0)) return HAB_ERR_INVALID_ARG;
+            }
+            texels.resize((size_t)tw * th);
+            for (size_t k = 0; k < texels.size(); ++k)
+                texels[k] = (uint32_t)m->texture[3 * k] | ((uint32_t)m->texture[3 * k + 1] << 8) |
+                            ((uint32_t)m->texture[3 * k + 2] << 16);
+        }
         std::vector<uint32_t> col(V);
         for (uint64_t k = 0; k < V; ++k) {
             if (m->colors)
@@ -184,25 +210,29 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
         const size_t bp = 12ull * V, bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
         const size_t bb = sizeof(float4) * cbox.size();
         const size_t bs = m->instances ? std::max<size_t>(4ull * T, 4) : 0;
+        const size_t buv = textured ? 8ull * V : 0;
+        const size_t btex = textured ? 4ull * m->tex_width * m->tex_height : 0;
         auto drop = [&]() {
-            (void)hipFree(s->pos);
-            (void)hipFree(s->col);
-            (void)hipFree(s->idx);
-            (void)hipFree(s->cbox);
-            (void)hipFree(s->inst);
+            free_scene_mem(s);
             delete s;
         };
         bool ok = hipMalloc((void **)&s->pos, bp) == hipSuccess &&
                   hipMalloc((void **)&s->col, bc) == hipSuccess &&
                   hipMalloc((void **)&s->idx, bi) == hipSuccess &&
                   hipMalloc((void **)&s->cbox, bb) == hipSuccess &&
-                  (!bs || hipMalloc((void **)&s->inst, bs) == hipSuccess);
+                  (!bs || hipMalloc((void **)&s->inst, bs) == hipSuccess) &&
+                  (!buv || hipMalloc((void **)&s->uv, buv) == hipSuccess) &&
+                  (!btex || hipMalloc((void **)&s->tex, btex) == hipSuccess);
         if (!ok) {
             (void)hipGetLastError();
             drop();
             return HAB_ERR_OUT_OF_MEMORY;
         }
-        s->bytes = bp + bc + bi + bb + bs;
+        s->bytes = bp + bc + bi + bb + bs + buv + btex;
+        if (textured) {
+            s->tw = m->tex_width;
+            s->th = m->tex_height;
+        }
         hipError_t e = hipMemcpyAsync(s->pos, m->positions, bp, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s->col, col.data(), bc, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && T)
@@ -210,6 +240,9 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
         if (e == hipSuccess) e = hipMemcpyAsync(s->cbox, cbox.data(), bb, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && bs && T)
             e = hipMemcpyAsync(s->inst, m->instances, 4ull * T, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && buv) e = hipMemcpyAsync(s->uv, m->uvs, buv, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && btex)
+            e = hipMemcpyAsync(s->tex, texels.data(), btex, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
             drop();
@@ -230,11 +263,7 @@ hab_status hab_scene_release(hab_context *ctx, hab_scene *scene)
         DeviceGuard g(ctx->device);
         // work that still reads the scene must finish first
         HAB_HIP(hipDeviceSynchronize());
-        (void)hipFree(scene->pos);
-        (void)hipFree(scene->col);
-        (void)hipFree(scene->idx);
-        (void)hipFree(scene->cbox);
-        (void)hipFree(scene->inst);
+        free_scene_mem(scene);
         ctx->scenes.erase(it);
         delete scene;
         return HAB_OK;

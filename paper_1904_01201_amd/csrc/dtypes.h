@@ -17,7 +17,7 @@ constexpr int kCluster = 64;                  // triangles per culling cluster (
 constexpr uint32_t kErrRange = 1u;            // a vertex snapped outside |X|,|Y| < 2^29
 constexpr uint32_t kErrResolve = 2u;          // a winning key could not be rebuilt
 
-// One view of a launch.  16-byte aligned; 224 bytes.
+// One view of a launch.  16-byte aligned; 240 bytes.
 struct alignas(16) DView {
     float p[3];
     float R[9];                 // row-major world-from-camera
@@ -47,8 +47,11 @@ struct alignas(16) DView {
     float noise_sigma;          // depth noise in 1/m (0: ideal depth)
     uint32_t pad2;
     uint64_t noise_seed;        // key of the per-pixel depth noise
+    const float *uv;            // [V][2] texture coordinates (textured scenes)
+    const uint32_t *tex;        // [tex_h][tex_w] packed RGB texels, or null
+    uint32_t tex_w, tex_h;      // powers of two
 };
-static_assert(sizeof(DView) == 224, "DView layout");
+static_assert(sizeof(DView) == 240, "DView layout");
 
 // Work queues of the raster stage, per tile size (8, 16, 32): `total`
 // items were appended by the scan.  The items are dealt to kQueues queues

@@ -932,6 +932,77 @@ __device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int
     return true;
 }
 
+// Textured colour: the texture coordinates ride through the clip and the
+// perspective-correct interpolation exactly as colours do (same fp32
+// sequence), then a bilinear fetch with texel centres at (k + 1/2) / size,
+// coordinates repeating.  For a power-of-two size and |u| size < 2^22,
+// u * size - 1/2 and its fraction are exact in fp32, so only the blend's
+// rounding differs from an fp64 evaluation.
+__device__ __forceinline__ void tex_bilinear(const DView &v, float u, float t, uint32_t rgb[3])
+{
+    const float x = u * (float)v.tex_w - 0.5f, y = t * (float)v.tex_h - 0.5f;
+    const float xf = floorf(x), yf = floorf(y);
+    const float fx = x - xf, fy = y - yf;
+    const int xi = (int)xf, yi = (int)yf;
+    const uint32_t wm = v.tex_w - 1u, hm = v.tex_h - 1u;
+    const uint32_t i0 = (uint32_t)xi & wm, i1 = (uint32_t)(xi + 1) & wm;
+    const uint32_t r0 = ((uint32_t)yi & hm) * v.tex_w, r1 = ((uint32_t)(yi + 1) & hm) * v.tex_w;
+    const auto *tex = gmem(v.tex);
+    const uint32_t t00 = tex[r0 + i0], t10 = tex[r0 + i1], t01 = tex[r1 + i0], t11 = tex[r1 + i1];
+    const float gx = 1.0f - fx, gy = 1.0f - fy;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float c00 = (float)unpack_rgb(t00, ch), c10 = (float)unpack_rgb(t10, ch);
+        const float c01 = (float)unpack_rgb(t01, ch), c11 = (float)unpack_rgb(t11, ch);
+        float val = gy * (gx * c00 + fx * c10) + fy * (gx * c01 + fx * c11);
+        val = rintf(val);
+        rgb[ch] = (uint32_t)fminf(fmaxf(val, 0.0f), 255.0f);
+    }
+}
+
+// resolve() for a textured scene: the same rebuild of the winner with the
+// texture coordinates as its two attributes.
+__device__ __forceinline__ bool resolve_tex(const DView &v, uint32_t key, int i, int j,
+                                            uint32_t rgb[3], float &depth)
+{
+    const uint32_t t = key >> 1;
+    const int sub = (int)(key & 1u);
+    float P[9];
+    uint32_t vid[3];
+    load_tri(v, t, P, vid);
+    Vtx<2> c0, c1, c2;
+    cam_xform(v, P[0], P[1], P[2], c0);
+    cam_xform(v, P[3], P[4], P[5], c1);
+    cam_xform(v, P[6], P[7], P[8], c2);
+    const auto *uv = gmem(v.uv);
+    c0.a[0] = uv[2u * vid[0]];
+    c0.a[1] = uv[2u * vid[0] + 1u];
+    c1.a[0] = uv[2u * vid[1]];
+    c1.a[1] = uv[2u * vid[1] + 1u];
+    c2.a[0] = uv[2u * vid[2]];
+    c2.a[1] = uv[2u * vid[2] + 1u];
+    SVtx<2> a = {}, b = {}, c = {};
+    long long A = 1;
+    bool rerr = false;
+    if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) {
+        rgb[0] = rgb[1] = rgb[2] = 0;
+        depth = 0.0f;
+        return false;
+    }
+    const long long px = 256ll * i + 128, py = 256ll * j + 128;
+    const long long E0 = edge_at(b.X, b.Y, c.X, c.Y, px, py);
+    const long long E1 = edge_at(c.X, c.Y, a.X, a.Y, px, py);
+    const long long E2 = edge_at(a.X, a.Y, b.X, b.Y, px, py);
+    const float w0 = (float)E0 * a.rw, w1 = (float)E1 * b.rw, w2 = (float)E2 * c.rw;
+    const float num = (w0 + w1) + w2;
+    const float invA = 1.0f / (float)A;
+    depth = 1.0f / (num * invA);
+    const float u = ((w0 * a.a[0] + w1 * b.a[0]) + w2 * c.a[0]) / num;
+    const float tv = ((w0 * a.a[1] + w1 * b.a[1]) + w2 * c.a[1]) / num;
+    tex_bilinear(v, u, tv, rgb);
+    return true;
+}
+
 template <int TS>
 // 6 waves per SIMD: the register budget (80 VGPRs) that lets enough
 // waves hide the LDS and staging latency; a 32-pixel tile's LDS allows 4.
@@ -1229,7 +1300,9 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
     }
     uint32_t rgb[3] = {0, 0, 0};
     float depth = 0.0f;
-    if (best_key != kNone && !resolve(v, best_key, pi, pj, rgb, depth)) atomicOr(err, kErrResolve);
+    if (best_key != kNone && !(v.tex ? resolve_tex(v, best_key, pi, pj, rgb, depth)
+                                     : resolve(v, best_key, pi, pj, rgb, depth)))
+        atomicOr(err, kErrResolve);
     const size_t p = (size_t)pj * v.W + (size_t)pi;
     if (v.noise_sigma > 0.0f && best_key != kNone) {
         const float rp = best_rho + v.noise_sigma * depth_noise_normal(v.noise_seed, (uint64_t)p);

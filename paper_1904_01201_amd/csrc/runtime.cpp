@@ -226,6 +226,10 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.sem = r.sem;
         d.noise_sigma = r.sensor.depth_noise_sigma;
         d.noise_seed = r.noise_seed;
+        d.uv = r.scene->uv;
+        d.tex = r.scene->tex;
+        d.tex_w = r.scene->tw;
+        d.tex_h = r.scene->th;
         d.tiles_x = cdiv(d.W, ts);
         d.tiles_y = cdiv(d.H, ts);
         d.tile_base = (uint32_t)tile_total;

@@ -26,6 +26,9 @@ struct Scene {
     uint32_t *idx = nullptr;    // [T][3]
     float4 *cbox = nullptr;     // [ceil(T/64)][2] cluster bounding boxes
     uint32_t *inst = nullptr;   // [T] instance id per triangle, or null
+    float *uv = nullptr;        // [V][2] texture coordinates, or null
+    uint32_t *tex = nullptr;    // [th][tw] packed RGB texels, or null
+    uint32_t tw = 0, th = 0;
     uint32_t V = 0, T = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     uint64_t bytes = 0;

@@ -83,9 +83,11 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------ scenes
-    def upload(self, positions, colors, indices, instances=None, stream=None) -> SceneHandle:
+    def upload(self, positions, colors, indices, instances=None, stream=None, uvs=None,
+               texture=None) -> SceneHandle:
         """instances: optional [T] uint32 instance id per triangle (needed
-        for the semantic output)."""
+        for the semantic output); uvs [V, 2] float32 with texture [th, tw, 3]
+        uint8 (powers of two): textured colour."""
         pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
         idx = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
         col = None if colors is None else np.ascontiguousarray(colors, np.uint8).reshape(-1, 3)
@@ -94,9 +96,20 @@ class Context:
             ins = np.ascontiguousarray(instances, np.uint32).reshape(-1)
             if ins.shape[0] != idx.shape[0]:
                 raise ValueError(f"instances: {ins.shape[0]} ids for {idx.shape[0]} triangles")
+        uv = tex = None
+        if (uvs is None) != (texture is None):
+            raise ValueError("uvs and texture go together")
+        if texture is not None:
+            uv = np.ascontiguousarray(uvs, np.float32).reshape(-1, 2)
+            tex = np.ascontiguousarray(texture, np.uint8)
+            if uv.shape[0] != pos.shape[0] or tex.ndim != 3 or tex.shape[2] != 3:
+                raise ValueError("uvs must be [V, 2] and texture [th, tw, 3]")
         d = B.MeshDesc(pos.ctypes.data, pos.shape[0], None if col is None else col.ctypes.data,
                        idx.ctypes.data if idx.size else None, idx.shape[0],
-                       ins.ctypes.data if ins is not None and ins.size else None)
+                       ins.ctypes.data if ins is not None and ins.size else None,
+                       None if uv is None else uv.ctypes.data,
+                       None if tex is None else tex.ctypes.data,
+                       0 if tex is None else tex.shape[1], 0 if tex is None else tex.shape[0])
         out = C.c_void_p()
         B.check(self.lib.hab_scene_upload(self.h, C.byref(d), _stream_ptr(stream), C.byref(out)),
                 "hab_scene_upload")
@@ -108,8 +121,12 @@ class Context:
         return s
 
     def upload_scene(self, scene, stream=None) -> SceneHandle:
+        """Upload a generated scene (its instance table, and its texture when
+        one is attached)."""
+        tex = getattr(scene, "texture", None)
         return self.upload(scene.positions, scene.colors, scene.indices,
-                           getattr(scene, "instances", None), stream=stream)
+                           getattr(scene, "instances", None), stream=stream,
+                           uvs=None if tex is None else scene.uvs, texture=tex)
 
     def release(self, scene: SceneHandle):
         B.check(self.lib.hab_scene_release(self.h, C.c_void_p(scene.ptr)), "hab_scene_release")

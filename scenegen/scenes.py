@@ -53,6 +53,12 @@ class Scene:
     # uint32 [T] object instance per triangle: one per structural surface
     # (floor, ceiling, wall piece), one per furniture box (its five faces)
     instances: np.ndarray | None = None
+    # float32 [V, 2] texture coordinates: each surface maps the texture
+    # planarly at TEXEL_PER_M texels per metre of a TEX_SIZE^2 texture,
+    # from a random offset; the texture itself ([TEX_SIZE, TEX_SIZE, 3]
+    # uint8) is attached by with_texture()
+    uvs: np.ndarray | None = None
+    texture: np.ndarray | None = None
 
     @property
     def num_triangles(self) -> int:
@@ -84,12 +90,18 @@ def _axis_coords(lo, hi, n):
     return c
 
 
-def _tessellate(rects, cell, rng_colors):
+TEX_SIZE = 2048
+TEXEL_PER_M = 256.0
+
+
+def _tessellate(rects, cell, rng_colors, rng_uv=None):
     """Grid-tessellate every rect.  Each quad (i,j)-(i+1,j+1) is split along
     its (i,j)->(i+1,j+1) diagonal.  Returns float64 positions, uint8 colours,
-    uint32 indices."""
+    uint32 indices and float32 texture coordinates (from ``rng_uv``'s
+    per-rect offsets; None without it)."""
     nu, nv = _counts(rects, cell)
-    pos_parts, col_parts, idx_parts = [], [], []
+    pos_parts, col_parts, idx_parts, uv_parts = [], [], [], []
+    rep = TEXEL_PER_M / TEX_SIZE          # texture periods per metre
     base = 0
     for k, r in enumerate(rects):
         a, b = int(nu[k]), int(nv[k])
@@ -115,11 +127,16 @@ def _tessellate(rects, cell, rng_colors):
         pos_parts.append(p)
         col_parts.append(col)
         idx_parts.append(tri)
+        if rng_uv is not None:
+            off = rng_uv.random(2)
+            uv = np.stack([off[0] + (U - r.u_lo) * rep, off[1] + (Vv - r.v_lo) * rep], axis=-1)
+            uv_parts.append(uv.reshape(-1, 2))
         base += p.shape[0]
     pos = np.concatenate(pos_parts, axis=0)
     col = np.concatenate(col_parts, axis=0)
     idx = np.concatenate(idx_parts, axis=0).astype(np.uint32)
-    return pos, col, idx
+    uvs = np.concatenate(uv_parts, axis=0).astype(np.float32) if uv_parts else None
+    return pos, col, idx, uvs
 
 
 def triangle_count(rects, cell) -> int:
@@ -174,13 +191,46 @@ def _instances(rects, cell, num_boxes):
 
 def _finish(rects, cell, seed, walls, boxes, bounds, discs, name, meta):
     rng_c = np.random.Generator(np.random.PCG64([seed, 7]))
-    pos, col, idx = _tessellate(rects, cell, rng_c)
+    rng_uv = np.random.Generator(np.random.PCG64([seed, 11]))
+    pos, col, idx, uvs = _tessellate(rects, cell, rng_c, rng_uv)
     return Scene(pos.astype(np.float32), col, idx,
                  np.asarray(walls, np.float64).reshape(-1, 4),
                  np.asarray(boxes, np.float64).reshape(-1, 4),
                  np.asarray(bounds, np.float64),
                  np.asarray(discs, np.float64).reshape(-1, 3), name, meta,
-                 _instances(rects, cell, len(boxes)))
+                 _instances(rects, cell, len(boxes)), uvs)
+
+
+def make_texture(seed: int, size: int = TEX_SIZE) -> np.ndarray:
+    """A seeded [size, size, 3] uint8 texture that tiles seamlessly: value
+    noise at periods of size/4 .. size/64 texels (bilinear upsampling of
+    periodic random grids) in three tinted channels, plus per-texel grain
+    of +-12, like a scanned surface's albedo."""
+    rng = np.random.Generator(np.random.PCG64([seed, 13]))
+    acc = np.zeros((size, size, 3), np.float64)
+    amp = 1.0
+    for cells in (4, 8, 16, 32, 64):
+        g = rng.random((cells, cells, 3))
+        t = (np.arange(size) + 0.5) * cells / size - 0.5
+        i0 = np.floor(t).astype(np.int64)
+        f = t - i0
+        a, b = i0 % cells, (i0 + 1) % cells
+        rows = g[a] * (1 - f)[:, None, None] + g[b] * f[:, None, None]
+        acc += amp * (rows[:, a] * (1 - f)[None, :, None] + rows[:, b] * f[None, :, None])
+        amp *= 0.55
+    acc /= sum(0.55 ** k for k in range(5))
+    tint = rng.uniform(0.6, 1.0, size=3)
+    val = 32 + 190 * acc * tint + rng.integers(-12, 13, size=(size, size, 3))
+    return np.clip(np.rint(val), 0, 255).astype(np.uint8)
+
+
+def with_texture(scene: Scene, seed: int | None = None, size: int = TEX_SIZE) -> Scene:
+    """The scene with a texture attached (its uvs already map it); the
+    default seed is a CRC of the scene's name."""
+    import zlib
+    from dataclasses import replace
+    s = seed if seed is not None else zlib.crc32(scene.name.encode())
+    return replace(scene, texture=make_texture(s, size))
 
 
 def make_room(seed: int, num_boxes: int = 20) -> Scene:

@@ -107,9 +107,11 @@ def oracle_compare_many(jobs, threads=None):
 
     def one(job):
         sc, sn, pose, g, st, what = job
+        tex = getattr(sc, "texture", None)
         o = oracle.render_view(sc.positions, sc.colors, sc.indices, sn.width, sn.height, pose,
                                hfov_deg=sn.hfov_deg, near_m=sn.near_m,
-                               instances=sc.instances if "semantic" in g else None)
+                               instances=sc.instances if "semantic" in g else None,
+                               uvs=None if tex is None else sc.uvs, texture=tex)
         compare(g, o, what)
         if st is not None:
             for k in ("survivors", "bbox_tests", "covered"):
