@@ -34,6 +34,10 @@ class Stats(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class Agent(C.Structure):
+    _fields_ = [("x", C.c_double), ("z", C.c_double), ("fx", C.c_double), ("fz", C.c_double)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -84,6 +88,9 @@ def _load():
             lib.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
             lib.or_depth_noise_normal.restype = C.c_double
             lib.or_depth_noise_normal.argtypes = [C.c_uint64, C.c_uint64]
+            lib.or_actuate.restype = C.c_int
+            lib.or_actuate.argtypes = [f32p, C.c_uint32, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, C.c_uint32, C.POINTER(Agent), u32p]
             lib.or_depth_noise.restype = C.c_int
             lib.or_depth_noise.argtypes = [f32p, u32p, C.c_uint32, C.c_uint32, C.c_double,
                                            C.c_uint64, f64p, f64p]
@@ -254,3 +261,25 @@ class OracleError(RuntimeError):
     def __init__(self, rc):
         super().__init__(f"oracle status {rc}")
         self.status = rc
+
+
+def actuate(segments, agents, actions, radius, step, turn_cos, turn_sin):
+    """Apply one action per agent (0 stop, 1 forward, 2 left, 3 right).
+    segments [n, 4] f32 obstacle segments; agents [N, 4] f64 (x, z, fx, fz).
+    Returns (new agents [N, 4] f64, collided [N] bool)."""
+    seg = np.ascontiguousarray(segments, np.float32).reshape(-1, 4)
+    ag = np.ascontiguousarray(agents, np.float64).reshape(-1, 4)
+    act = np.asarray(actions, np.uint32).reshape(-1)
+    out = ag.copy()
+    hit = np.zeros(ag.shape[0], bool)
+    lib = _load()
+    flag = C.c_uint32()
+    for k in range(ag.shape[0]):
+        a = Agent(*out[k])
+        rc = lib.or_actuate(_ptr(seg, C.c_float), seg.shape[0], float(radius), float(step),
+                            float(turn_cos), float(turn_sin), int(act[k]), C.byref(a), C.byref(flag))
+        if rc != OR_OK:
+            raise OracleError(rc)
+        out[k] = (a.x, a.z, a.fx, a.fz)
+        hit[k] = bool(flag.value)
+    return out, hit

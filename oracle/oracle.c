@@ -607,3 +607,155 @@ int or_depth_noise(const float *rho, const uint32_t *tri, uint32_t W, uint32_t H
         }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Actuation and collision (Sec. 4 "Agent embodiment and action space" and
+ * "Collision dynamics"): the agent is a vertical cylinder of 0.2 m diameter
+ * that turns by 10 degrees or moves 0.25 m forward in a continuous state
+ * space; a move that meets an obstacle makes partial or no progress and may
+ * slide along it.  The paper gives no algorithm; the written definition:
+ *
+ *   - the agent is a disc of radius r on the floor plane (x, z); its heading
+ *     is the unit forward vector (fx, fz) (yaw 0 looks along -z);
+ *   - obstacles are line segments in that plane (the boundary of the free
+ *     floor: walls and furniture footprints);
+ *   - turn left / right: (fx, fz) <- (fx c + fz s, fz c - fx s) with
+ *     (c, s) = (cos, +-sin) of the turn angle, given by the caller;
+ *   - forward: the motion D = step (fx, fz) runs through at most 4 passes of
+ *     collide-and-slide: find the earliest contact time t in [0, 1] at which
+ *     the moving disc reaches distance r from a segment while approaching it
+ *     (the segment's interior or an endpoint; earliest t, then the lower
+ *     segment index, then interior before first before second endpoint);
+ *     without one the disc moves by D and stops; with one it moves by
+ *     max(0, t - skin / |D|) D (skin = 1e-6 m), the rest of the motion
+ *     loses its component along the contact normal, and the next pass
+ *     continues with what is left.  Motion left after the last pass is
+ *     dropped.
+ * Everything is fp64, one IEEE rounding per operation in the order written.
+ * ---------------------------------------------------------------------- */
+#define OR_SLIDE_PASSES 4
+#define OR_SKIN 1e-6
+
+typedef struct {
+    double x, z;   /* position on the floor plane, metres */
+    double fx, fz; /* unit forward vector */
+} or_agent;
+
+/* Earliest approach contact of the disc at (px, pz) moving by (dx, dz)
+ * (not zero) against the segments; returns 1 and (t, contact normal) if
+ * there is one with t <= 1. */
+static int first_contact(const float *seg, uint32_t nseg, double r, double px, double pz,
+                         double dx, double dz, double *t_out, double *nx_out, double *nz_out)
+{
+    const double a = dx * dx + dz * dz;
+    int found = 0;
+    double bt = 0.0, bnx = 0.0, bnz = 0.0;
+    for (uint32_t k = 0; k < nseg; ++k) {
+        const double ax = seg[4 * (size_t)k], az = seg[4 * (size_t)k + 1];
+        const double bx = seg[4 * (size_t)k + 2], bz = seg[4 * (size_t)k + 3];
+        const double ex = bx - ax, ez = bz - az;
+        const double L2 = ex * ex + ez * ez;
+        if (L2 > 0.0) {
+            /* the segment's interior: the disc's centre reaches distance r
+             * from the line with its foot inside the segment */
+            const double L = sqrt(L2);
+            double nx = -ez / L, nz = ex / L;
+            double d0 = (px - ax) * nx + (pz - az) * nz;
+            double rate = dx * nx + dz * nz;
+            if (d0 < 0.0) {
+                d0 = -d0;
+                rate = -rate;
+                nx = -nx;
+                nz = -nz;
+            }
+            if (rate < 0.0) {
+                double t = (d0 - r) / -rate;
+                if (t < 0.0) t = 0.0;
+                if (t <= 1.0) {
+                    const double cx = px + t * dx, cz = pz + t * dz;
+                    const double s = ((cx - ax) * ex + (cz - az) * ez) / L2;
+                    if (s >= 0.0 && s <= 1.0 && (!found || t < bt)) {
+                        found = 1;
+                        bt = t;
+                        bnx = nx;
+                        bnz = nz;
+                    }
+                }
+            }
+        }
+        for (int e = 0; e < 2; ++e) {
+            /* an endpoint: |p + t D - q| = r, first root, approaching */
+            const double qx = e ? bx : ax, qz = e ? bz : az;
+            const double gx = px - qx, gz = pz - qz;
+            const double b = gx * dx + gz * dz;
+            if (!(b < 0.0)) continue;
+            const double c = gx * gx + gz * gz - r * r;
+            double t;
+            if (c <= 0.0) {
+                t = 0.0;
+            } else {
+                const double disc = b * b - a * c;
+                if (disc < 0.0) continue;
+                t = (-b - sqrt(disc)) / a;
+            }
+            if (t > 1.0) continue;
+            const double cx = px + t * dx - qx, cz = pz + t * dz - qz;
+            const double len = sqrt(cx * cx + cz * cz);
+            if (!(len > 0.0)) continue;
+            if (!found || t < bt) {
+                found = 1;
+                bt = t;
+                bnx = cx / len;
+                bnz = cz / len;
+            }
+        }
+    }
+    *t_out = bt;
+    *nx_out = bnx;
+    *nz_out = bnz;
+    return found;
+}
+
+/* One action of one agent.  action: 0 stop, 1 forward, 2 turn left, 3 turn
+ * right.  *collided is set to 1 when a forward move met an obstacle. */
+int or_actuate(const float *seg, uint32_t nseg, double radius, double step, double turn_cos,
+               double turn_sin, uint32_t action, or_agent *ag, uint32_t *collided)
+{
+    if (!ag || !collided || (nseg && !seg) || action > 3) return OR_ERR_INVALID_ARG;
+    *collided = 0;
+    if (action == 2 || action == 3) {
+        const double s = action == 2 ? turn_sin : -turn_sin;
+        const double fx = ag->fx * turn_cos + ag->fz * s;
+        const double fz = ag->fz * turn_cos - ag->fx * s;
+        ag->fx = fx;
+        ag->fz = fz;
+        return OR_OK;
+    }
+    if (action == 0) return OR_OK;
+    double px = ag->x, pz = ag->z;
+    double dx = step * ag->fx, dz = step * ag->fz;
+    for (int pass = 0; pass < OR_SLIDE_PASSES; ++pass) {
+        const double a = dx * dx + dz * dz;
+        if (!(a > 0.0)) break;
+        double t, nx, nz;
+        if (!first_contact(seg, nseg, radius, px, pz, dx, dz, &t, &nx, &nz)) {
+            px += dx;
+            pz += dz;
+            break;
+        }
+        *collided = 1;
+        double ts = t - OR_SKIN / sqrt(a);
+        if (ts < 0.0) ts = 0.0;
+        px += ts * dx;
+        pz += ts * dz;
+        double rx = (1.0 - ts) * dx, rz = (1.0 - ts) * dz;
+        const double dn = rx * nx + rz * nz;
+        rx -= dn * nx;
+        rz -= dn * nz;
+        dx = rx;
+        dz = rz;
+    }
+    ag->x = px;
+    ag->z = pz;
+    return OR_OK;
+}

@@ -75,9 +75,14 @@ def copy_scale(d: str, counter: str) -> float:
     return (COPY_BYTES / 1024.0) / kib
 
 
+# the sources the render kernels are compiled from: a change to any of them
+# invalidates recorded traffic
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "raster_math.h", "dtypes.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(HERE, "csrc"))):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()

@@ -136,3 +136,41 @@ def random_walks(scene: Scene, num_agents: int, steps: int, seed: int) -> np.nda
             z = np.where(move, nz, z)
         out[s] = poses_from_states(x, z, yaw)
     return out
+
+
+# ---------------------------------------------------------------------------
+# inputs of the actuation step: obstacle segments and agent states
+# ---------------------------------------------------------------------------
+def nav_segments(scene: Scene) -> np.ndarray:
+    """float32 [n, 4] obstacle segments (x0, z0, x1, z1) on the floor plane:
+    the scene's walls, then the four edges of every box footprint."""
+    parts = [np.asarray(scene.walls, np.float64).reshape(-1, 4)]
+    if scene.boxes.shape[0]:
+        b = scene.boxes
+        x0, z0, x1, z1 = b[:, 0], b[:, 1], b[:, 2], b[:, 3]
+        edges = np.stack([np.stack([x0, z0, x1, z0], 1), np.stack([x1, z0, x1, z1], 1),
+                          np.stack([x1, z1, x0, z1], 1), np.stack([x0, z1, x0, z0], 1)], 1)
+        parts.append(edges.reshape(-1, 4))
+    return np.concatenate(parts, 0).astype(np.float32)
+
+
+def agents_from_states(x, z, yaw) -> np.ndarray:
+    """float64 [n, 4] agent states (x, z, fx, fz): position and the unit
+    forward vector of heading ``yaw`` (yaw 0 looks along -z)."""
+    yaw = np.asarray(yaw, np.float64)
+    return np.stack([np.asarray(x, np.float64), np.asarray(z, np.float64),
+                     -np.sin(yaw), -np.cos(yaw)], axis=1)
+
+
+def poses_from_agents(agents, y=SENSOR_HEIGHT) -> np.ndarray:
+    """float32 [n, 12] camera poses of agent states (no trigonometry: the
+    rotation's columns are the camera's right (-fz, 0, fx), up and back
+    (-fx, 0, -fz) vectors)."""
+    a = np.asarray(agents, np.float64).reshape(-1, 4)
+    fx, fz = a[:, 2], a[:, 3]
+    zero, one = np.zeros_like(fx), np.ones_like(fx)
+    out = np.stack([a[:, 0], np.full_like(fx, y), a[:, 1],
+                    -fz, zero, -fx,
+                    zero, one, zero,
+                    fx, zero, -fz], axis=1)
+    return out.astype(np.float32)
