@@ -129,6 +129,47 @@ def other_workloads(ctx, a):
     return out
 
 
+def actuation_leg(ctx, w, a):
+    """The agent step before rendering: batched actuation with
+    collide-and-slide for 16,384 agents per scene of the bench workload
+    (65,536 agents), uniformly random actions (forward twice as likely as
+    each turn), timed over the bench's step count."""
+    import torch
+    from scenegen import agents_from_states, nav_segments
+    from scenegen.walks import random_free_states
+    per = 16384
+    navs = [ctx.nav_upload(nav_segments(s)) for s in w.scenes]
+    states, owner = [], []
+    for i, s in enumerate(w.scenes):
+        x, z, yaw = random_free_states(s, per, seed=500 + i)
+        states.append(agents_from_states(x, z, yaw))
+        owner += [i] * per
+    n = per * len(w.scenes)
+    ag = torch.from_numpy(np.concatenate(states)).cuda()
+    rng = np.random.default_rng(3)
+    steps = max(a.steps, 1)
+    acts = torch.from_numpy(rng.choice([1, 1, 2, 3], size=(steps + a.warmup, n)).astype(np.uint8)).cuda()
+    hit = torch.empty(n, dtype=torch.uint8, device="cuda")
+    poses = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    nav_of = ctx.nav_array([navs[i] for i in owner])
+    for s in range(a.warmup):
+        ctx.actuate(nav_of, ag, acts[s], hit, poses)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ctx.actuate(nav_of, ag, acts[a.warmup + s], hit, poses)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for nv in navs:
+        ctx.nav_release(nv)
+    out = {"agents": n, "scenes": len(w.scenes), "segments": [int(nv.num_segments) for nv in navs],
+           "steps": steps, "agent_steps_per_s": round(n * steps / el), "ms_per_step": round(1e3 * el / steps, 4),
+           "path": "hab_actuate (fp64 collide-and-slide over a uniform 0.5 m grid of obstacle segments)"}
+    log(f"actuation: {out['agent_steps_per_s']:.3g} agent steps/s ({out['ms_per_step']} ms per "
+        f"{n}-agent step)")
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -412,6 +453,7 @@ def main():
 
     # ---------------------------------------------------- the other workloads
     others = {} if a.no_other_workloads else other_workloads(ctx, a)
+    actuation = actuation_leg(ctx, w, a)
 
     # ---------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -480,6 +522,7 @@ def main():
         "hbm_roofline": hbm,
         "cpu_baseline": cpu,
         "other_workloads": others,
+        "actuation": actuation,
         "paper_context": {"rgbd_256_fps_1proc": 1042, "rgbd_256_fps_5proc": 1774,
                           "hardware": "Titan Xp + Xeon E5-2690 v4, OpenGL, Matterport3D scene"},
     }

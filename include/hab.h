@@ -237,6 +237,66 @@ hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sen
 hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t num_views,
                             const hab_render_opts *opts, hipStream_t stream);
 
+/* ---------------------------------------------------------- actuation */
+/* The agent step before rendering (Sec. 4 "Agent embodiment and action
+ * space", "Collision dynamics"): an agent is a vertical cylinder (a disc of
+ * radius r on the floor plane) that stops, turns left or right, or moves
+ * forward in a continuous state space; a forward move that meets an
+ * obstacle makes partial or no progress and may slide along it.
+ *
+ * Obstacles are line segments on the floor plane (x0, z0, x1, z1), the
+ * boundary of the free floor, uploaded once per scene. */
+typedef struct hab_nav hab_nav;
+
+/* segments: host [num_segments][4] float, metres (finite; a zero-length
+ * segment is a point obstacle); num_segments may be 0.  The segments are
+ * copied. */
+hab_status hab_nav_upload(hab_context *ctx, const float *segments, uint32_t num_segments,
+                          hab_nav **out);
+hab_status hab_nav_release(hab_context *ctx, hab_nav *nav);
+
+/* Agent state: position on the floor plane and the unit forward vector
+ * (yaw 0 looks along -z: (fx, fz) = (-sin yaw, -cos yaw)). */
+typedef struct {
+    double x, z;
+    double fx, fz;
+} hab_agent;
+
+enum { HAB_ACT_STOP = 0, HAB_ACT_FORWARD = 1, HAB_ACT_LEFT = 2, HAB_ACT_RIGHT = 3 };
+
+/* radius > 0 (the paper's agent: 0.1 m), forward_m >= 0 (0.25 m), and the
+ * rotation of one turn, (turn_cos, turn_sin) = (cos, sin) of the turn angle
+ * (10 degrees), all finite. */
+typedef struct {
+    double radius;
+    double forward_m;
+    double turn_cos, turn_sin;
+} hab_actuation;
+
+/* Apply one action to each of num_agents agents, in fp64:
+ *   - left / right: (fx, fz) <- (fx c + fz s, fz c - fx s), s = +-turn_sin;
+ *   - forward: the motion D = forward_m (fx, fz) runs through at most 4
+ *     passes of collide-and-slide against the agent's segments: the earliest
+ *     contact time t in [0, 1] at which the moving disc reaches distance
+ *     radius from a segment while approaching it (its interior or an
+ *     endpoint; earliest t, then lower segment index, then interior before
+ *     first before second endpoint); without one the disc moves by D; with
+ *     one it moves by max(0, t - 1e-6 / |D|) D, the rest of the motion loses
+ *     its component along the contact normal and the next pass continues
+ *     with it; motion left after the last pass is dropped;
+ *   - stop, and any action value above 3: no change.
+ * navs: host array [num_agents], the obstacles of each agent's scene.
+ * agents [num_agents] (in/out), actions [num_agents] uint8, collided
+ * [num_agents] uint8 (1 when a forward move met an obstacle; or NULL) and
+ * poses [num_agents][12] float (the camera pose after the step: position
+ * (x, camera_height, z), rotation with columns right (-fz, 0, fx), up and
+ * back (-fx, 0, -fz); or NULL) are device pointers; the call is
+ * asynchronous on the stream. */
+hab_status hab_actuate(hab_context *ctx, const hab_nav *const *navs, uint32_t num_agents,
+                       hab_agent *agents, const uint8_t *actions, uint8_t *collided,
+                       float *poses, float camera_height, const hab_actuation *params,
+                       hipStream_t stream);
+
 /* ---------------------------------------------------------- stepper */
 /* A fixed batch composition captured once as a HIP graph.  Each step
  * takes new poses (host array [num_views]), validates them, stages them

@@ -34,7 +34,9 @@ EXPORTED = [
     "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
     "hab_profile_enable", "hab_profile_phases", "hab_profile_read",
+    "hab_nav_upload", "hab_nav_release", "hab_actuate",
 ]
+ACT_STOP, ACT_FORWARD, ACT_LEFT, ACT_RIGHT = 0, 1, 2, 3
 PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "raster16",
           "raster32", "resolve"]
 
@@ -74,6 +76,11 @@ class View(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("sensor", C.POINTER(Sensor)), ("pose", Pose),
                 ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_tri", C.c_void_p),
                 ("out_semantic", C.c_void_p), ("noise_seed", C.c_uint64)]
+
+
+class Actuation(C.Structure):
+    _fields_ = [("radius", C.c_double), ("forward_m", C.c_double), ("turn_cos", C.c_double),
+                ("turn_sin", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -153,6 +160,9 @@ def load():
             "hab_profile_enable": [vp, C.c_int],
             "hab_profile_phases": [vp, C.c_uint32],
             "hab_profile_read": [vp, C.POINTER(PhaseTimes)],
+            "hab_nav_upload": [vp, vp, u32, C.POINTER(vp)],
+            "hab_nav_release": [vp, vp],
+            "hab_actuate": [vp, C.POINTER(vp), u32, vp, vp, vp, vp, f32, C.POINTER(Actuation), vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)

@@ -10,36 +10,6 @@
 
 using namespace habmi;
 
-namespace {
-
-// Make ctx's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-template <class F>
-hab_status guarded(F &&f)
-{
-    try {
-        return f();
-    } catch (const std::bad_alloc &) {
-        return HAB_ERR_OUT_OF_MEMORY;
-    } catch (...) {
-        return HAB_ERR_DEVICE;
-    }
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -112,6 +82,7 @@ hab_status hab_shutdown(hab_context *ctx)
             delete static_cast<hab_scene *>(s);
         }
         ctx->scenes.clear();
+        release_navs(ctx);
         for (auto &ps : ctx->prof_sets)
             for (auto &e : ps.ev) (void)hipEventDestroy(e);
         if (ctx->err) (void)hipFree(ctx->err);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "../../include/hab.h"
@@ -18,6 +19,34 @@ namespace habmi {
         hipError_t e_ = (x);                        \
         if (e_ != hipSuccess) return HAB_ERR_DEVICE; \
     } while (0)
+
+// Make a context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Run an entry point's body with no exception crossing the C boundary.
+template <class F>
+hab_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return HAB_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return HAB_ERR_DEVICE;
+    }
+}
 
 struct Scene {
     int device = 0;
@@ -130,6 +159,14 @@ struct hab_context {
     uint32_t prof_phase_mask = 0x1FFu;   // phases timed while profiling is on
     std::vector<ProfSet> prof_sets;
     size_t prof_used = 0;
+    // actuation: obstacle sets and the workspace of hab_actuate; the last
+    // call's per-agent sets, whose descriptor table and per-agent indices
+    // stay in act_ws's arena until a call with other sets (a release
+    // clears it)
+    std::vector<hab_nav *> navs;
+    habmi::Workspace act_ws;
+    std::vector<const hab_nav *> act_last;
+    size_t act_last_off = 0;
 };
 
 struct hab_scene : habmi::Scene {};
@@ -137,6 +174,7 @@ struct hab_scene : habmi::Scene {};
 namespace habmi {
 
 hab_status validate_sensor(const hab_sensor *s);
+void release_navs(hab_context *ctx);   // frees every obstacle set (shutdown)
 hab_status validate_pose(const Scene *sc, const hab_sensor *s, const hab_pose *p);
 uint32_t class_key(const Scene *sc, const hab_sensor *s);
 uint32_t choose_tile(hab_context *ctx, const Scene *sc, const hab_sensor *s, const PlanOpts &o,

@@ -4,6 +4,7 @@ loop and the autotuner.  Thin wrappers over the C ABI (include/hab.h)."""
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -51,6 +52,12 @@ def check_output(name, t, n, sensor):
 
 
 @dataclass
+class NavHandle:
+    ptr: int
+    num_segments: int
+
+
+@dataclass
 class SceneHandle:
     ptr: int
     num_vertices: int
@@ -64,6 +71,12 @@ class Context:
     """One device context (scenes stay resident in HBM until released)."""
 
     def __init__(self, device: int = 0):
+        # torch provides the device memory and streams: bring its runtime up
+        # on the device first (initialised after the library, it may not
+        # enumerate the GPU)
+        torch = _torch()
+        if torch.cuda.is_available():
+            torch.cuda.set_device(device)
         self.lib = B.load()
         self.device = device
         h = C.c_void_p()
@@ -277,6 +290,52 @@ class Context:
         B.check(self.lib.hab_profile_read(self.h, C.byref(t)), "hab_profile_read")
         return {name: {"ms": t.ms[k], "launches": int(t.launches[k])}
                 for k, name in enumerate(B.PHASES) if t.launches[k]}
+
+    # ------------------------------------------------------------ actuation
+    def nav_upload(self, segments) -> "NavHandle":
+        """Obstacle segments [n, 4] float32 (x0, z0, x1, z1) of one scene."""
+        seg = np.ascontiguousarray(segments, np.float32).reshape(-1, 4)
+        out = C.c_void_p()
+        B.check(self.lib.hab_nav_upload(self.h, seg.ctypes.data if seg.size else None,
+                                        seg.shape[0], C.byref(out)), "hab_nav_upload")
+        return NavHandle(out.value, seg.shape[0])
+
+    def nav_release(self, nav: "NavHandle"):
+        B.check(self.lib.hab_nav_release(self.h, C.c_void_p(nav.ptr)), "hab_nav_release")
+
+    @staticmethod
+    def actuation(radius=0.1, forward_m=0.25, turn_deg=10.0) -> B.Actuation:
+        t = math.radians(turn_deg)
+        return B.Actuation(float(radius), float(forward_m), math.cos(t), math.sin(t))
+
+    @staticmethod
+    def nav_array(navs):
+        """A reusable argument for actuate(): the per-agent NavHandles as the
+        C array the library takes."""
+        return (C.c_void_p * len(navs))(*[nv.ptr for nv in navs])
+
+    def actuate(self, navs, agents, actions, collided=None, poses=None, camera_height=1.5,
+                params=None, stream=None):
+        """One action per agent.  navs: a NavHandle per agent (or a
+        nav_array() of them); agents [n, 4] float64, actions [n] uint8,
+        collided [n] uint8, poses [n, 12] float32: contiguous CUDA tensors
+        (agents updated in place)."""
+        torch = _torch()
+        n = len(navs)
+        for name, t, dt, per in (("agents", agents, torch.float64, 4), ("actions", actions, torch.uint8, 1),
+                                 ("collided", collided, torch.uint8, 1), ("poses", poses, torch.float32, 12)):
+            if t is None:
+                if name in ("agents", "actions"):
+                    raise ValueError(f"{name} is required")
+                continue
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+                    and t.dtype == dt and t.numel() == n * per):
+                raise ValueError(f"{name}: need a contiguous CUDA {dt} tensor of {n * per} elements")
+        arr = navs if isinstance(navs, C.Array) else self.nav_array(navs)
+        p = params if params is not None else self.actuation()
+        B.check(self.lib.hab_actuate(self.h, arr, n, _ptr(agents), _ptr(actions), _ptr(collided),
+                                     _ptr(poses), float(camera_height), C.byref(p),
+                                     _stream_ptr(stream)), "hab_actuate")
 
     # ------------------------------------------------------------ stepper
     def stepper(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None):
