@@ -331,6 +331,37 @@ def main():
     st.close()
     log(f"batched graph: {fps_graph:.0f} frames/s")
 
+    # ---------------------------------------------------- env loop
+    # the whole environment step on the device: actuation of the 64 agents
+    # (random actions, collide-and-slide) feeding the captured render step
+    from scenegen import agents_from_states, nav_segments, poses_from_agents
+    from scenegen.walks import random_free_states
+    navs_h = [ctx.nav_upload(nav_segments(s)) for s in w.scenes]
+    ag_np = np.concatenate([agents_from_states(*random_free_states(w.scenes[w.env_scene[e]], 1, seed=900 + e))
+                            for e in range(E)])
+    ag = torch.from_numpy(ag_np).cuda()
+    env_poses = torch.from_numpy(poses_from_agents(ag_np)).cuda()
+    nav_of = ctx.nav_array([navs_h[w.env_scene[e]] for e in range(E)])
+    acts = torch.from_numpy(np.random.default_rng(4).choice([1, 1, 2, 3], size=(a.steps + a.warmup, E))
+                            .astype(np.uint8)).cuda()
+    st = ctx.stepper([(hs[w.env_scene[e]], sensor, poses_from_agents(ag_np[e:e + 1])[0], rgb[e], depth[e], None)
+                      for e in range(E)], tile_size=a.tile_size)
+    for s in range(a.warmup):
+        ctx.actuate(nav_of, ag, acts[s], None, env_poses)
+        st.step_device(env_poses)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        ctx.actuate(nav_of, ag, acts[a.warmup + s], None, env_poses)
+        st.step_device(env_poses)
+    torch.cuda.synchronize()
+    t_env = time.perf_counter() - t0
+    st.close()
+    for nv in navs_h:
+        ctx.nav_release(nv)
+    fps_env = E * a.steps / t_env
+    log(f"env loop (actuation + graph render, device poses): {fps_env:.0f} frames/s")
+
     # ---------------------------------------------------- per-view
     pv_steps = max(1, min(a.per_view_steps, a.steps))
     for e in range(E):
@@ -509,6 +540,7 @@ def main():
                    "tile_size": a.tile_size or "autotuned", "autotune": tuned},
         "batched_fps": round(fps_batch, 1),
         "batched_graph_fps": round(fps_graph, 1),
+        "env_loop_fps": round(fps_env, 1),
         "batched_rgbd_semantic_fps": round(fps_sem, 1),
         "batched_rgb_noisy_depth_fps": round(fps_noisy, 1),
         "batched_textured_rgbd_fps": round(fps_tex, 1),

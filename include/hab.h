@@ -307,6 +307,16 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
                               const hab_render_opts *opts, hipStream_t stream,
                               hab_stepper **out);
 hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t stream);
+/* As hab_stepper_step with the poses already on the device: poses is a
+ * device array [num_views][12] float (position, then the row-major
+ * rotation, in the order of the views given at creation), e.g. the poses
+ * output of hab_actuate, so an agent step and its render run without a host
+ * round trip.  The poses are read when the step runs on the stream, so
+ * they must stay valid (and unchanged) until then.  No host-side pose check
+ * is possible: a pose whose scene leaves the fixed-point domain drops the
+ * affected triangles and sets the sticky HAB_ERR_RANGE bit of hab_get_error
+ * instead. */
+hab_status hab_stepper_step_device(hab_stepper *st, const float *poses, hipStream_t stream);
 hab_status hab_stepper_destroy(hab_stepper *st);
 
 /* ---------------------------------------------------------- serving */

@@ -30,7 +30,7 @@ EXPORTED = [
     "hab_init", "hab_shutdown", "hab_status_string", "hab_get_error",
     "hab_scene_upload", "hab_scene_release", "hab_scene_info", "hab_sensor_spec",
     "hab_render", "hab_render_ex", "hab_render_batch",
-    "hab_stepper_create", "hab_stepper_step", "hab_stepper_destroy",
+    "hab_stepper_create", "hab_stepper_step", "hab_stepper_step_device", "hab_stepper_destroy",
     "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
     "hab_profile_enable", "hab_profile_phases", "hab_profile_read",
@@ -149,6 +149,7 @@ def load():
             "hab_stepper_create": [vp, C.POINTER(View), u32, C.POINTER(RenderOpts), vp,
                                    C.POINTER(vp)],
             "hab_stepper_step": [vp, C.POINTER(Pose), vp],
+            "hab_stepper_step_device": [vp, vp, vp],
             "hab_stepper_destroy": [vp],
             "hab_server_create": [vp, C.POINTER(ServerCfg), C.POINTER(vp)],
             "hab_server_submit": [vp, C.POINTER(View), C.POINTER(C.c_uint64)],

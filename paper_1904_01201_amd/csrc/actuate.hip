@@ -5,10 +5,14 @@
 // is stated with hab_actuate in hab.h.
 //
 // Layout: each obstacle set carries a uniform grid built at upload (0.5 m
-// cells; a cell lists every segment whose bounding box overlaps it).  One
-// thread moves one agent: per pass it visits the cells under the box swept
-// by the disc (grown by the radius and a 0.1 mm margin) and runs the fp64
-// contact test on the segments there whose own box meets the swept box.
+// cells; a cell lists every segment whose bounding box overlaps it).  A
+// group of G lanes moves one agent (G = 64 for small batches, where one
+// lane per agent would leave the chip idle and expose the dependent
+// cell -> list -> segment loads; fewer for large ones): per pass each lane
+// takes every G-th entry of the cells under the box swept by the disc
+// (grown by the radius and a 0.1 mm margin), runs the fp64 contact test on
+// the segments whose own box meets the swept box, and the group reduces
+// the lanes' earliest contacts with shuffles.
 // A segment outside that box cannot be touched during the move, and the
 // winning contact is chosen by an explicit order (time, then segment index,
 // then interior before first before second endpoint), so the result is the
@@ -137,6 +141,28 @@ __device__ __forceinline__ int cell_of(float q, float o, float inv_h, uint32_t g
     return (int)fminf(fmaxf(c, 0.0f), (float)(g - 1u));
 }
 
+// Lexicographic minimum of the group's contacts (found first, then t, then
+// code): every lane ends with the group's winner.
+template <int G>
+__device__ __forceinline__ void group_min(bool &found, double &bt, uint32_t &bcode, double &bnx, double &bnz)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        const int of = __shfl_xor((int)found, off, G);
+        const double ot = __shfl_xor(bt, off, G);
+        const uint32_t oc = (uint32_t)__shfl_xor((int)bcode, off, G);
+        const double ox = __shfl_xor(bnx, off, G), oz = __shfl_xor(bnz, off, G);
+        if (of && (!found || ot < bt || (ot == bt && oc < bcode))) {
+            found = true;
+            bt = ot;
+            bcode = oc;
+            bnx = ox;
+            bnz = oz;
+        }
+    }
+}
+
+template <int G>
 __global__ __launch_bounds__(kActBlock) void k_actuate(const NavDesc *__restrict__ navs,
                                                        const uint32_t *__restrict__ nav_of,
                                                        uint32_t n, hab_agent *__restrict__ agents,
@@ -144,7 +170,10 @@ __global__ __launch_bounds__(kActBlock) void k_actuate(const NavDesc *__restrict
                                                        uint8_t *__restrict__ collided,
                                                        float *__restrict__ poses, ActParams P)
 {
-    const uint32_t k = blockIdx.x * kActBlock + threadIdx.x;
+    const uint32_t gid = blockIdx.x * kActBlock + threadIdx.x;
+    const uint32_t k = gid / G, lane = gid % G;
+    // whole groups leave together (n agents fill n * G lanes; groups never
+    // straddle a wave), so the shuffles below see only live lanes
     if (k >= n) return;
     hab_agent g = agents[k];
     const uint32_t act = actions[k];
@@ -178,7 +207,7 @@ __global__ __launch_bounds__(kActBlock) void k_actuate(const NavDesc *__restrict
                     for (int cx = cx0; cx <= cx1; ++cx) {
                         const uint32_t c = (uint32_t)cz * D.gx + (uint32_t)cx;
                         const uint32_t i1 = D.cell_start[c + 1];
-                        for (uint32_t i = D.cell_start[c]; i < i1; ++i) {
+                        for (uint32_t i = D.cell_start[c] + lane; i < i1; i += G) {
                             const uint32_t j = D.items[i];
                             const float4 sg = D.seg[j];
                             if (fminf(sg.x, sg.z) > qx1 || fmaxf(sg.x, sg.z) < qx0 ||
@@ -188,6 +217,7 @@ __global__ __launch_bounds__(kActBlock) void k_actuate(const NavDesc *__restrict
                         }
                     }
             }
+            if (G > 1) group_min<G>(found, bt, bcode, bnx, bnz);
             if (!found) {
                 px += dx;
                 pz += dz;
@@ -208,6 +238,7 @@ __global__ __launch_bounds__(kActBlock) void k_actuate(const NavDesc *__restrict
         g.x = px;
         g.z = pz;
     }
+    if (lane != 0) return;
     agents[k] = g;
     if (collided) collided[k] = hit ? 1 : 0;
     if (poses) {
@@ -396,8 +427,21 @@ hab_status hab_actuate(hab_context *ctx, const hab_nav *const *navs, uint32_t n,
         ActParams P{params->radius, params->forward_m, params->turn_cos, params->turn_sin, camera_height};
         const NavDesc *dt = static_cast<const NavDesc *>(ws.arena);
         const uint32_t *di = reinterpret_cast<const uint32_t *>(static_cast<char *>(ws.arena) + ctx->act_last_off);
-        hipLaunchKernelGGL(k_actuate, dim3((n + kActBlock - 1) / kActBlock), dim3(kActBlock), 0, stream, dt, di,
-                           n, agents, actions, collided, poses, P);
+        // lanes per agent: enough groups to fill the chip (~64k lanes)
+        const uint32_t G = n <= 1024 ? 64u : n <= 4096 ? 16u : n <= 16384 ? 4u : 1u;
+        const dim3 grid((uint32_t)((uint64_t(n) * G + kActBlock - 1) / kActBlock));
+        if (G == 64)
+            hipLaunchKernelGGL(k_actuate<64>, grid, dim3(kActBlock), 0, stream, dt, di, n, agents, actions,
+                               collided, poses, P);
+        else if (G == 16)
+            hipLaunchKernelGGL(k_actuate<16>, grid, dim3(kActBlock), 0, stream, dt, di, n, agents, actions,
+                               collided, poses, P);
+        else if (G == 4)
+            hipLaunchKernelGGL(k_actuate<4>, grid, dim3(kActBlock), 0, stream, dt, di, n, agents, actions,
+                               collided, poses, P);
+        else
+            hipLaunchKernelGGL(k_actuate<1>, grid, dim3(kActBlock), 0, stream, dt, di, n, agents, actions,
+                               collided, poses, P);
         HAB_HIP(hipGetLastError());
         HAB_HIP(hipEventRecord(ws.done, stream));
         ws.has_done = true;

@@ -278,6 +278,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         plan.off_lpre[c] = off;
         off = align256(off + 4 * lpre[c].size());
     }
+    plan.off_ctl = off;          // control slot (the stepper's device-pose pointer)
+    off = align256(off + 16);
     plan.desc_bytes = off;
     desc.resize(off);
     std::memcpy(desc.data() + plan.off_views, dv.data(), sizeof(DView) * n);

@@ -129,6 +129,7 @@ struct Plan {
     size_t off_skey = 0, off_sbox = 0, off_bins = 0;
     size_t off_titem = 0, off_queue = 0, off_items[3] = {0, 0, 0}, off_partial[3] = {0, 0, 0};
     size_t off_pairs = 0;
+    size_t off_ctl = 0;              // 16 B control slot in the descriptor block
     std::vector<uint32_t> order;     // sorted position -> caller index
     uint32_t n = 0;
 };

@@ -12,6 +12,22 @@
 
 using namespace habmi;
 
+// Device-pose steps: copy each view's pose (caller order) into its
+// descriptor (planned order) after the descriptor upload; the poses'
+// address arrives with the descriptors, in the plan's control slot.
+__global__ void k_patch_poses(DView *__restrict__ views, const float *const *__restrict__ ctl,
+                              const uint32_t *__restrict__ order, uint32_t n)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float *src = ctl[0] + 12ull * order[k];
+    DView &v = views[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v.p[a] = src[a];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) v.R[a] = src[3 + a];
+}
+
 struct hab_stepper {
     hab_context *ctx = nullptr;
     int device = 0;
@@ -21,6 +37,8 @@ struct hab_stepper {
     void *arena = nullptr;
     void *host[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t exec_dev[2] = {nullptr, nullptr};   // with the pose patch
+    uint32_t *dorder = nullptr;   // [n] planned position -> caller index
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool pending[2] = {false, false};
     hipEvent_t last = nullptr;
@@ -36,6 +54,7 @@ static void destroy(hab_stepper *st)
     for (int b = 0; b < 2; ++b) {
         if (st->pending[b]) (void)hipEventSynchronize(st->ev[b]);
         if (st->exec[b]) (void)hipGraphExecDestroy(st->exec[b]);
+        if (st->exec_dev[b]) (void)hipGraphExecDestroy(st->exec_dev[b]);
         if (st->ev[b]) (void)hipEventDestroy(st->ev[b]);
         if (st->host[b]) (void)hipHostFree(st->host[b]);
     }
@@ -43,6 +62,7 @@ static void destroy(hab_stepper *st)
     if (st->last) (void)hipEventDestroy(st->last);
     if (st->cap) (void)hipStreamDestroy(st->cap);
     if (st->arena) (void)hipFree(st->arena);
+    if (st->dorder) (void)hipFree(st->dorder);
     delete st;
 }
 
@@ -84,6 +104,12 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
             return fail(HAB_ERR_OUT_OF_MEMORY);
         }
         bind_plan(st->plan, st->arena, ctx->err);
+        if (hipMalloc((void **)&st->dorder, 4ull * n) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HAB_ERR_OUT_OF_MEMORY);
+        }
+        if (hipMemcpy(st->dorder, st->plan.order.data(), 4ull * n, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(HAB_ERR_DEVICE);
         if (hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess)
             return fail(HAB_ERR_DEVICE);
         if (hipEventCreateWithFlags(&st->last, hipEventDisableTiming) != hipSuccess)
@@ -97,20 +123,30 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
             std::memcpy(st->host[b], st->desc.data(), st->plan.desc_bytes);
             if (hipEventCreateWithFlags(&st->ev[b], hipEventDisableTiming) != hipSuccess)
                 return fail(HAB_ERR_DEVICE);
-            hipGraph_t g = nullptr;
-            if (hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return fail(HAB_ERR_DEVICE);
-            hipError_t e = hipMemcpyAsync(st->arena, st->host[b], st->plan.desc_bytes,
-                                          hipMemcpyHostToDevice, st->cap);
-            if (e == hipSuccess) e = launch_render(st->plan.L, st->cap);
-            hipError_t e2 = hipStreamEndCapture(st->cap, &g);
-            if (e != hipSuccess || e2 != hipSuccess || !g) {
-                if (g) (void)hipGraphDestroy(g);
-                return fail(HAB_ERR_DEVICE);
+            for (int dev = 0; dev < 2; ++dev) {
+                hipGraph_t g = nullptr;
+                if (hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return fail(HAB_ERR_DEVICE);
+                hipError_t e = hipMemcpyAsync(st->arena, st->host[b], st->plan.desc_bytes,
+                                              hipMemcpyHostToDevice, st->cap);
+                if (e == hipSuccess && dev) {
+                    DView *views = reinterpret_cast<DView *>(static_cast<char *>(st->arena) + st->plan.off_views);
+                    const float *const *ctl =
+                        reinterpret_cast<const float *const *>(static_cast<char *>(st->arena) + st->plan.off_ctl);
+                    hipLaunchKernelGGL(k_patch_poses, dim3((n + 255) / 256), dim3(256), 0, st->cap, views, ctl,
+                                       (const uint32_t *)st->dorder, n);
+                    e = hipGetLastError();
+                }
+                if (e == hipSuccess) e = launch_render(st->plan.L, st->cap);
+                hipError_t e2 = hipStreamEndCapture(st->cap, &g);
+                if (e != hipSuccess || e2 != hipSuccess || !g) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return fail(HAB_ERR_DEVICE);
+                }
+                e = hipGraphInstantiate(dev ? &st->exec_dev[b] : &st->exec[b], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return fail(HAB_ERR_DEVICE);
             }
-            e = hipGraphInstantiate(&st->exec[b], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return fail(HAB_ERR_DEVICE);
         }
         (void)stream;
         if (prev >= 0) (void)hipSetDevice(prev);
@@ -121,14 +157,20 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
     }
 }
 
-hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t stream)
+}  // extern "C"
+
+// One step: host poses (validated, staged with the descriptors) or device
+// poses (their address staged in the control slot, patched into the
+// descriptors by the graph).
+static hab_status step_common(hab_stepper *st, const hab_pose *poses, const float *dposes,
+                              hipStream_t stream)
 {
-    if (!st || !poses) return HAB_ERR_INVALID_ARG;
     const uint32_t n = (uint32_t)st->req.size();
-    for (uint32_t k = 0; k < n; ++k) {
-        hab_status s = validate_pose(st->req[k].scene, &st->req[k].sensor, &poses[k]);
-        if (s != HAB_OK) return s;
-    }
+    if (poses)
+        for (uint32_t k = 0; k < n; ++k) {
+            hab_status s = validate_pose(st->req[k].scene, &st->req[k].sensor, &poses[k]);
+            if (s != HAB_OK) return s;
+        }
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (hipSetDevice(st->device) != hipSuccess) return HAB_ERR_DEVICE;
@@ -141,16 +183,19 @@ hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t 
             st->pending[b] = false;
         }
         char *h = static_cast<char *>(st->host[b]);
+        if (dposes) std::memcpy(h + st->plan.off_ctl, &dposes, sizeof dposes);
         for (uint32_t k = 0; k < n; ++k) {
             DView *d = reinterpret_cast<DView *>(h + st->plan.off_views) + k;
-            const hab_pose &p = poses[st->plan.order[k]];
-            std::memcpy(d->p, p.position, sizeof d->p);
-            std::memcpy(d->R, p.rotation, sizeof d->R);
+            if (poses) {
+                const hab_pose &p = poses[st->plan.order[k]];
+                std::memcpy(d->p, p.position, sizeof d->p);
+                std::memcpy(d->R, p.rotation, sizeof d->R);
+            }
             d->noise_seed = st->req[st->plan.order[k]].noise_seed + st->steps;
         }
         if (st->has_last && st->last_stream != stream &&
             hipStreamWaitEvent(stream, st->last, 0) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
-        if (hipGraphLaunch(st->exec[b], stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
+        if (hipGraphLaunch(dposes ? st->exec_dev[b] : st->exec[b], stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
         if (hipEventRecord(st->ev[b], stream) != hipSuccess) { rc = HAB_ERR_DEVICE; break; }
         st->pending[b] = true;
         ++st->steps;
@@ -160,6 +205,20 @@ hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t 
     } while (0);
     if (prev >= 0) (void)hipSetDevice(prev);
     return rc;
+}
+
+extern "C" {
+
+hab_status hab_stepper_step(hab_stepper *st, const hab_pose *poses, hipStream_t stream)
+{
+    if (!st || !poses) return HAB_ERR_INVALID_ARG;
+    return step_common(st, poses, nullptr, stream);
+}
+
+hab_status hab_stepper_step_device(hab_stepper *st, const float *poses, hipStream_t stream)
+{
+    if (!st || !poses) return HAB_ERR_INVALID_ARG;
+    return step_common(st, nullptr, poses, stream);
 }
 
 hab_status hab_stepper_destroy(hab_stepper *st)

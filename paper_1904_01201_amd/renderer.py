@@ -368,6 +368,18 @@ class Stepper:
             raise ValueError("one pose per view")
         B.check(self.ctx.lib.hab_stepper_step(self.h, pc, _stream_ptr(stream)), "hab_stepper_step")
 
+    def step_device(self, poses, stream=None):
+        """A step whose poses are already on the device: a contiguous CUDA
+        float32 tensor [n, 12] in the views' order (e.g. actuate()'s poses
+        output)."""
+        torch = _torch()
+        n = len(self.views)
+        if not (isinstance(poses, torch.Tensor) and poses.is_cuda and poses.is_contiguous()
+                and poses.dtype == torch.float32 and poses.numel() == 12 * n):
+            raise ValueError(f"poses: need a contiguous CUDA float32 tensor of {12 * n} elements")
+        B.check(self.ctx.lib.hab_stepper_step_device(self.h, _ptr(poses), _stream_ptr(stream)),
+                "hab_stepper_step_device")
+
     def close(self):
         if self.h:
             B.check(self.ctx.lib.hab_stepper_destroy(self.h), "hab_stepper_destroy")

@@ -152,3 +152,54 @@ def test_argument_errors(ctx):
         ctx.actuate([nav, nav], ag.float(), act)
     ctx.nav_release(nav)
     assert ctx.get_error() == 0
+
+
+def test_device_resident_env_loop(ctx):
+    """Agents step on the GPU and the captured stepper renders from the poses
+    they produce, without a host round trip: every step's images equal an
+    eager batch rendered from the same poses copied to the host, for 16
+    environments over two apartments, host-pose steps interleaved."""
+    import torch
+    note("actuation: device-resident env loop")
+    scenes = [make_apartment(seed=41, target_T=30_000), make_apartment(seed=42, target_T=30_000)]
+    hs = [ctx.upload_scene(s) for s in scenes]
+    navs_h = [ctx.nav_upload(nav_segments(s)) for s in scenes]
+    owner = np.arange(16) % 2
+    parts = [agents_from_states(*random_free_states(scenes[i], 8, seed=60 + i)) for i in range(2)]
+    agents = np.empty((16, 4))
+    for i in range(2):
+        agents[owner == i] = parts[i]
+    sn = ctx.sensor(128, 96, 90.0, 0.01, depth_noise_sigma=0.05)
+    outs = [ctx.alloc(sn, 1, tri=True) for _ in range(16)]
+    poses0 = poses_from_agents(agents)
+    items = [(hs[owner[e]], sn, poses0[e], outs[e]["rgb"], outs[e]["depth"], outs[e]["tri"], None, 10 * e)
+             for e in range(16)]
+    st = ctx.stepper(items)
+    navs = ctx.nav_array([navs_h[i] for i in owner])
+    ag = torch.from_numpy(agents).cuda()
+    poses = torch.empty((16, 12), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(3)
+    for step in range(8):
+        act = torch.from_numpy(rng.choice([1, 1, 2, 3], size=16).astype(np.uint8)).cuda()
+        ctx.actuate(navs, ag, act, None, poses)
+        if step % 3 == 2:
+            torch.cuda.synchronize()
+            st.step(poses.cpu().numpy())
+        else:
+            st.step_device(poses)
+        torch.cuda.synchronize()
+        got = [{k: o[k].clone() for k in o} for o in outs]
+        hp = poses.cpu().numpy()
+        ref = [ctx.alloc(sn, 1, tri=True) for _ in range(16)]
+        ctx.render_batch([(hs[owner[e]], sn, hp[e], ref[e]["rgb"], ref[e]["depth"], ref[e]["tri"], None,
+                           10 * e + step) for e in range(16)])
+        torch.cuda.synchronize()
+        for e in range(16):
+            for k in ("rgb", "depth", "tri"):
+                assert torch.equal(got[e][k], ref[e][k]), (step, e, k)
+    st.close()
+    assert ctx.get_error() == 0
+    for h in hs:
+        ctx.release(h)
+    for nv in navs_h:
+        ctx.nav_release(nv)
