@@ -62,7 +62,7 @@ hab_status hab_init(int device, hab_context **out)
 // Device memory of a scene (every pointer may be null).
 static void free_scene_mem(Scene *s)
 {
-    (void)hipFree(s->pos);
+    (void)hipFree(s->tpos);
     (void)hipFree(s->col);
     (void)hipFree(s->idx);
     (void)hipFree(s->cbox);
@@ -178,7 +178,15 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             s->lo[a] = lo[a];
             s->hi[a] = hi[a];
         }
-        const size_t bp = 12ull * V, bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
+        // positions are stored per triangle (three float4 per triangle) so
+        // that kernels load a triangle without the index -> position hop
+        std::vector<float4> tri(3 * (size_t)std::max<uint32_t>(T, 1), make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+        for (uint64_t t = 0; t < T; ++t)
+            for (int k = 0; k < 3; ++k) {
+                const float *q = m->positions + 3ull * m->indices[3ull * t + k];
+                tri[3 * t + k] = make_float4(q[0], q[1], q[2], 0.0f);
+            }
+        const size_t bp = sizeof(float4) * tri.size(), bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
         const size_t bb = sizeof(float4) * cbox.size();
         const size_t bs = m->instances ? std::max<size_t>(4ull * T, 4) : 0;
         const size_t buv = textured ? 8ull * V : 0;
@@ -187,7 +195,7 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             free_scene_mem(s);
             delete s;
         };
-        bool ok = hipMalloc((void **)&s->pos, bp) == hipSuccess &&
+        bool ok = hipMalloc((void **)&s->tpos, bp) == hipSuccess &&
                   hipMalloc((void **)&s->col, bc) == hipSuccess &&
                   hipMalloc((void **)&s->idx, bi) == hipSuccess &&
                   hipMalloc((void **)&s->cbox, bb) == hipSuccess &&
@@ -204,7 +212,7 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             s->tw = m->tex_width;
             s->th = m->tex_height;
         }
-        hipError_t e = hipMemcpyAsync(s->pos, m->positions, bp, hipMemcpyHostToDevice, stream);
+        hipError_t e = hipMemcpyAsync(s->tpos, tri.data(), bp, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s->col, col.data(), bc, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && T)
             e = hipMemcpyAsync(s->idx, m->indices, 12ull * T, hipMemcpyHostToDevice, stream);

@@ -125,20 +125,30 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gmem_out(T *p)
     return (__attribute__((address_space(1))) T *)p;
 }
 
+// Triangle t's vertex positions: three independent 16-byte loads from the
+// per-triangle copy (no dependent index -> position load).  T < 2^30
+// (checked at upload): 32-bit element offsets.
+__device__ __forceinline__ void load_pos(const DView &v, uint32_t t, float P[9])
+{
+    using f32x4 = float __attribute__((ext_vector_type(4)));
+    const auto *p = reinterpret_cast<const __attribute__((address_space(1))) f32x4 *>(gmem(v.tpos)) + 3u * t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const f32x4 q = p[k];
+        P[3 * k + 0] = q.x;
+        P[3 * k + 1] = q.y;
+        P[3 * k + 2] = q.z;
+    }
+}
+
+// Positions and the vertex indices (for per-vertex attributes).
 __device__ __forceinline__ void load_tri(const DView &v, uint32_t t, float P[9], uint32_t vid[3])
 {
-    // T, V < 2^30 (checked at upload): 32-bit element offsets
     const auto *ix = gmem(v.idx) + 3u * t;
     vid[0] = ix[0];
     vid[1] = ix[1];
     vid[2] = ix[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const auto *p = gmem(v.pos) + 3u * vid[k];
-        P[3 * k + 0] = p[0];
-        P[3 * k + 1] = p[1];
-        P[3 * k + 2] = p[2];
-    }
+    load_pos(v, t, P);
 }
 
 // ------------------------------------------------------------ k_reset
@@ -365,9 +375,8 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
         }
 #pragma unroll
         for (uint32_t j = 0; j < kRun; ++j) {
-            uint32_t vid[3];
             if (valid[j]) {
-                load_tri(v, t[j], P[j], vid);
+                load_pos(v, t[j], P[j]);
             } else {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) P[j][k] = 0.0f;
@@ -725,8 +734,7 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     const uint32_t t = key >> 1;
     const int sub = (int)(key & 1u);
     float P[9];
-    uint32_t vid[3];
-    load_tri(v, t, P, vid);
+    load_pos(v, t, P);
     Vtx<0> c0, c1, c2;
     cam_xform(v, P[0], P[1], P[2], c0);
     cam_xform(v, P[3], P[4], P[5], c1);

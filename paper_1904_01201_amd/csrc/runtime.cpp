@@ -215,7 +215,7 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         d.H = r.sensor.height;
         d.T = r.scene->T;
         d.ts_log2 = ts_log2(ts);
-        d.pos = r.scene->pos;
+        d.tpos = r.scene->tpos;
         d.col = r.scene->col;
         d.idx = r.scene->idx;
         d.cbox = r.scene->cbox;
