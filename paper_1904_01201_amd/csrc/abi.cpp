@@ -178,15 +178,15 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             s->lo[a] = lo[a];
             s->hi[a] = hi[a];
         }
-        // positions are stored per triangle (three float4 per triangle) so
+        // positions are stored per triangle (nine floats per triangle) so
         // that kernels load a triangle without the index -> position hop
-        std::vector<float4> tri(3 * (size_t)std::max<uint32_t>(T, 1), make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+        std::vector<float> tri(9 * (size_t)std::max<uint32_t>(T, 1), 0.0f);
         for (uint64_t t = 0; t < T; ++t)
             for (int k = 0; k < 3; ++k) {
                 const float *q = m->positions + 3ull * m->indices[3ull * t + k];
-                tri[3 * t + k] = make_float4(q[0], q[1], q[2], 0.0f);
+                for (int a = 0; a < 3; ++a) tri[9 * t + 3 * k + a] = q[a];
             }
-        const size_t bp = sizeof(float4) * tri.size(), bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
+        const size_t bp = sizeof(float) * tri.size(), bc = 4ull * V, bi = std::max<size_t>(12ull * T, 12);
         const size_t bb = sizeof(float4) * cbox.size();
         const size_t bs = m->instances ? std::max<size_t>(4ull * T, 4) : 0;
         const size_t buv = textured ? 8ull * V : 0;

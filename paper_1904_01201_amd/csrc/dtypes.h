@@ -25,7 +25,7 @@ struct alignas(16) DView {
     uint32_t W, H;
     uint32_t T;                 // triangles of the scene
     uint32_t ts_log2;           // tile size 8/16/32 -> 3/4/5
-    const float4 *tpos;         // [T][3] vertex positions per triangle (x, y, z, 0)
+    const float *tpos;          // [T][3][3] vertex positions per triangle
     const uint32_t *col;        // [V] packed R | G<<8 | B<<16
     const uint32_t *idx;        // [T][3]
     uint8_t *rgb;               // [H][W][3] or null

@@ -125,20 +125,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gmem_out(T *p)
     return (__attribute__((address_space(1))) T *)p;
 }
 
-// Triangle t's vertex positions: three independent 16-byte loads from the
-// per-triangle copy (no dependent index -> position load).  T < 2^30
-// (checked at upload): 32-bit element offsets.
+// Triangle t's vertex positions: nine consecutive floats of the
+// per-triangle copy, independent loads (no dependent index -> position
+// load).  With T up to 2^30, 9 t can exceed 32 bits: a 64-bit offset.
 __device__ __forceinline__ void load_pos(const DView &v, uint32_t t, float P[9])
 {
-    using f32x4 = float __attribute__((ext_vector_type(4)));
-    const auto *p = reinterpret_cast<const __attribute__((address_space(1))) f32x4 *>(gmem(v.tpos)) + 3u * t;
+    const auto *p = gmem(v.tpos) + 9ull * t;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const f32x4 q = p[k];
-        P[3 * k + 0] = q.x;
-        P[3 * k + 1] = q.y;
-        P[3 * k + 2] = q.z;
-    }
+    for (int i = 0; i < 9; ++i) P[i] = p[i];
 }
 
 // Positions and the vertex indices (for per-vertex attributes).

@@ -50,7 +50,7 @@ hab_status guarded(F &&f)
 
 struct Scene {
     int device = 0;
-    float4 *tpos = nullptr;     // [T][3] vertex positions per triangle (x, y, z, 0)
+    float *tpos = nullptr;      // [T][3][3] vertex positions per triangle
     uint32_t *col = nullptr;    // [V] packed
     uint32_t *idx = nullptr;    // [T][3]
     float4 *cbox = nullptr;     // [ceil(T/64)][2] cluster bounding boxes
