@@ -237,7 +237,7 @@ def main():
         print(json.dumps({"copy_calibration": True, "bytes_per_copy": n, "copies": 4}), flush=True)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build renders on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this renderer runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU sharding is a design note only)"}))
         sys.exit(2)
 
