@@ -1302,9 +1302,16 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
     }
     uint32_t rgb[3] = {0, 0, 0};
     float depth = 0.0f;
-    if (best_key != kNone && !(v.tex ? resolve_tex(v, best_key, pi, pj, rgb, depth)
-                                     : resolve(v, best_key, pi, pj, rgb, depth)))
-        atomicOr(err, kErrResolve);
+    if (best_key != kNone) {
+        if (!v.rgb) {
+            // no colour wanted: the depth is the reciprocal of the winning
+            // key's 1/w, the same value the rebuild would compute
+            depth = 1.0f / best_rho;
+        } else if (!(v.tex ? resolve_tex(v, best_key, pi, pj, rgb, depth)
+                           : resolve(v, best_key, pi, pj, rgb, depth))) {
+            atomicOr(err, kErrResolve);
+        }
+    }
     const size_t p = (size_t)pj * v.W + (size_t)pi;
     if (v.noise_sigma > 0.0f && best_key != kNone) {
         const float rp = best_rho + v.noise_sigma * depth_noise_normal(v.noise_seed, (uint64_t)p);
