@@ -298,9 +298,11 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
                                                        uint32_t *__restrict__ err)
 {
     __shared__ uint32_t pre[kMaxViews];
-    __shared__ uint32_t wtot[kSetupBlock / 64];
     __shared__ uint32_t bkey[kSetupBlock / 64][kSetupBuf];
     __shared__ uint2 bbox[kSetupBlock / 64][kSetupBuf];
+    // the prologue scan's per-wave totals live in the first survivor buffer
+    // (dead until the barrier below): 40 KiB per block, four blocks per CU
+    uint32_t *const wtot = bkey[0];
     uint32_t total;
     {
         const uint32_t seg = (nviews + kSetupBlock - 1) / kSetupBlock;

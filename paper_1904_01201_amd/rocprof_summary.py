@@ -17,7 +17,10 @@ Per kernel the trace gives the average duration over the last N launches
 (the timed steps); the counter runs give per-dispatch averages.  VALU issue
 utilisation is SQ_INSTS_VALU * 4 / (SIMDs * cycles): a wave64 VALU
 instruction holds a 16-lane SIMD for 4 cycles; cycles are GRBM_GUI_ACTIVE
-over the 8 XCDs.
+over the 8 XCDs.  Occupancy (waves resident per SIMD, averaged over the
+dispatch) is 4 * SQ_WAVE_CYCLES / (SIMDs * cycles): the counter advances once
+per 4 cycles per resident wave (checked against the raster, launched
+persistently at 6 waves per SIMD).
 """
 from __future__ import annotations
 
@@ -109,9 +112,9 @@ def main(argv=None):
         lines += ["Commands:", "", *[f"    {c}" for c in a.command.split(" ;; ")], ""]
     lines += [f"Copy calibration: FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f} "
               f"(256 MiB device copy = 262144 KiB each way)", ""]
-    lines += ["| kernel | launches (timed) | avg us (timed) | VALU instr | VALU issue util | SALU instr | "
+    lines += ["| kernel | launches (timed) | avg us (timed) | VALU instr | VALU issue util | waves/SIMD | SALU instr | "
               "LDS instr | LDS bank-conflict cycles | HBM read MB | HBM write MB |",
-              "|---|---|---|---|---|---|---|---|---|---|"]
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
     order = sorted(dur, key=lambda k: -sum(dur[k][-a.steps:]))
     traffic = None
     for k in order:
@@ -123,12 +126,14 @@ def main(argv=None):
         valu, salu, lds = avg("SQ_INSTS_VALU"), avg("SQ_INSTS_SALU"), avg("SQ_INSTS_LDS")
         gui = avg("GRBM_GUI_ACTIVE")
         util = valu * 4 / (SIMDS * gui / XCDS) if valu and gui else None
+        wcyc = avg("SQ_WAVE_CYCLES")
+        occ = wcyc * 4 / (SIMDS * gui / XCDS) if wcyc and gui else None
         conf = avg("SQ_LDS_BANK_CONFLICT")
         fetch, write = avg("FETCH_SIZE"), avg("WRITE_SIZE")
         rd = fetch * 1024 * sf / 1e6 if fetch is not None else None
         wr = write * 1024 * sw / 1e6 if write is not None else None
         f = lambda x, p=3: "-" if x is None else (f"{x:.{p}g}" if isinstance(x, float) else str(x))
-        lines.append(f"| `{k}` | {len(d)} | {sum(d) / len(d):.1f} | {f(valu)} | {f(util, 2)} | {f(salu)} | "
+        lines.append(f"| `{k}` | {len(d)} | {sum(d) / len(d):.1f} | {f(valu)} | {f(util, 2)} | {f(occ, 2)} | {f(salu)} | "
                      f"{f(lds)} | {f(conf)} | {f(rd, 4)} | {f(wr, 4)} |")
         if k == a.kernel and rd is not None and wr is not None:
             traffic = {"kernel": k, "avg_launch_us": sum(d) / len(d), "hbm_read_bytes": rd * 1e6,
