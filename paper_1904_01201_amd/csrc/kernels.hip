@@ -484,9 +484,11 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                                                    uint32_t *__restrict__ bins)
 {
     __shared__ uint32_t pre[kMaxViews];
-    __shared__ uint32_t wtot[kBinBlock / 64];
     __shared__ uint32_t hist[kLdsTiles];   // low 16 bits: count, high 16 bits: rank cursor
     __shared__ uint32_t lbase[SCATTER ? kLdsTiles : 1];
+    // the prefix scan's per-wave totals live in the histogram (first
+    // written after the scan's closing barrier): 32 KiB per scatter block
+    uint32_t *const wtot = hist;
     const uint32_t total = build_item_prefix(ctr, nviews, pre, wtot);
     const uint32_t tid = threadIdx.x;
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
