@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(const DView *__restrict__
                                                        uint2 *__restrict__ sbox,
                                                        uint32_t *__restrict__ err)
 {
-    __shared__ uint32_t pre[kMaxViews];
+    extern __shared__ uint32_t pre[];      // [nviews]: sized at launch
     __shared__ uint32_t bkey[kSetupBlock / 64][kSetupBuf];
     __shared__ uint2 bbox[kSetupBlock / 64][kSetupBuf];
     // the prologue scan's per-wave totals live in the first survivor buffer
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                                                    uint32_t *__restrict__ tile_cursor,
                                                    uint32_t *__restrict__ bins)
 {
-    __shared__ uint32_t pre[kMaxViews];
+    extern __shared__ uint32_t pre[];      // [nviews]: sized at launch
     __shared__ uint32_t hist[kLdsTiles];   // low 16 bits: count, high 16 bits: rank cursor
     __shared__ uint32_t lbase[SCATTER ? kLdsTiles : 1];
     // the prefix scan's per-wave totals live in the histogram (first
@@ -1377,11 +1377,12 @@ hipError_t launch_render(const LaunchPlan &L, hipStream_t s)
     mark(L, 1, s);
     mark(L, 2, s);
     hipLaunchKernelGGL(k_cull, dim3(L.cull_blocks, L.nviews), dim3(kCullBlock), 0, s, L.views, L.ctr, L.pairs);
-    hipLaunchKernelGGL(k_setup, dim3(L.setup_grid), dim3(kSetupBlock), 0, s, L.views, L.nviews, L.ctr,
+    const size_t pre_bytes = 4u * (size_t)L.nviews;   // the per-view prefix in LDS
+    hipLaunchKernelGGL(k_setup, dim3(L.setup_grid), dim3(kSetupBlock), pre_bytes, s, L.views, L.nviews, L.ctr,
                        L.pairs, L.skey, L.sbox, L.err);
     mark(L, 3, s);
     mark(L, 4, s);
-    hipLaunchKernelGGL(k_bin<false>, dim3(L.bin_grid), dim3(kBinBlock), 0, s, L.views, L.nviews,
+    hipLaunchKernelGGL(k_bin<false>, dim3(L.bin_grid), dim3(kBinBlock), pre_bytes, s, L.views, L.nviews,
                        L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.tile_cursor, L.bins);
     mark(L, 5, s);
     mark(L, 6, s);
@@ -1390,7 +1391,7 @@ hipError_t launch_render(const LaunchPlan &L, hipStream_t s)
                        L.items[2]);
     mark(L, 7, s);
     mark(L, 8, s);
-    hipLaunchKernelGGL(k_bin<true>, dim3(L.bin_grid), dim3(kBinBlock), 0, s, L.views, L.nviews,
+    hipLaunchKernelGGL(k_bin<true>, dim3(L.bin_grid), dim3(kBinBlock), pre_bytes, s, L.views, L.nviews,
                        L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.tile_cursor, L.bins);
     mark(L, 9, s);
     for (int k = 0; k < L.nraster; ++k) {
