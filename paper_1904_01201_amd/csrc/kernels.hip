@@ -289,9 +289,9 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(const DView *__restrict__ v
 constexpr uint32_t kRun = 4;
 constexpr uint32_t kSetupBuf = 2 * kRun * kCluster;   // survivors one wave buffers in LDS
 
-// 5 waves per SIMD (at most 96 VGPRs): the loads of four clusters per lane
-// need the registers, and more waves hide their latency better than
-// fewer wider ones (6 waves spill)
+// 5 waves per SIMD (at most 96 VGPRs, a few of them spilled): more waves
+// hide the latency of the four clusters' loads per lane better than four
+// waves without spills; at 6 waves the spills cost more than they hide
 __global__ __launch_bounds__(kSetupBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_setup(const DView *__restrict__ views,
                                                        uint32_t nviews,
                                                        DViewCounters *__restrict__ ctr,
