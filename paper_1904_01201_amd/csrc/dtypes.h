@@ -8,6 +8,7 @@ namespace habmi {
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kOverflow = 0xFFFFFFFFu;   // tile offset marker: list not stored
 constexpr int kSetupBlock = 256;              // threads per block in setup
+constexpr int kSetupWavesPerSimd = 5;         // setup's register budget; its grid is one round of it
 constexpr int kBinBlock = 256;                // threads per block in count/scatter
 constexpr int kBinItems = 4;                  // survivors per thread in count/scatter
 constexpr int kScanBlock = 1024;

@@ -292,7 +292,7 @@ constexpr uint32_t kSetupBuf = 2 * kRun * kCluster;   // survivors one wave buff
 // 5 waves per SIMD (at most 96 VGPRs, a few of them spilled): more waves
 // hide the latency of the four clusters' loads per lane better than four
 // waves without spills; at 6 waves the spills cost more than they hide
-__global__ __launch_bounds__(kSetupBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_setup(const DView *__restrict__ views,
+__global__ __launch_bounds__(kSetupBlock) __attribute__((amdgpu_waves_per_eu(kSetupWavesPerSimd))) void k_setup(const DView *__restrict__ views,
                                                        uint32_t nviews,
                                                        DViewCounters *__restrict__ ctr,
                                                        const uint32_t *__restrict__ vis_clusters,

@@ -331,8 +331,11 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     uint32_t max_t = 0;
     for (uint32_t k = 0; k < n; ++k) max_t = std::max(max_t, dv[k].T);
     L.cull_blocks = std::max<uint32_t>(1, cdiv(cdiv(max_t, kCluster), 256));
+    // one round of resident setup blocks (the waves take static shares of
+    // the work, so a second partial round would only add a tail)
+    const uint64_t setup_resident = (uint64_t)kSetupWavesPerSimd * 4 / (kSetupBlock / 64);
     L.setup_grid = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>((npairs + 15) / 16, 8ull * (ctx ? ctx->cu_count : 256)));
+        1, std::min<uint64_t>((npairs + 15) / 16, setup_resident * (ctx ? ctx->cu_count : 256)));
     L.ntiles = (uint32_t)tile_total;
     uint64_t ub = 0;
     for (uint32_t k = 0; k < n; ++k) ub += cdiv(dv[k].surv_cap, kBinBlock * kBinItems);
