@@ -450,6 +450,13 @@ __device__ __forceinline__ uint32_t build_item_prefix(const DViewCounters *ctr, 
     return total;
 }
 
+// LDS slot of tile i in the per-chunk tile arrays: the low five bits are
+// XORed with the next five, a permutation within each aligned run of 32
+// slots.  Vertically adjacent tiles (32 per row at 256 px / 8 px tiles) would
+// otherwise share an LDS bank, and a wave's boxes touch such columns of tiles
+// together; the arrays are cleared up to the next multiple of 32.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+
 __device__ __forceinline__ uint32_t find_view(const uint32_t *pre, uint32_t nviews, uint32_t item)
 {
     uint32_t lo = 0, hi = nviews - 1;
@@ -504,7 +511,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
         const uint32_t ts = v.ts_log2, tiles_x = v.tiles_x, nt = v.tiles_x * v.tiles_y;
         const uint32_t tile_base = v.tile_base, bin_base = v.bin_base, surv_base = v.surv_base;
         if (nt <= kLdsTiles) {
-            for (uint32_t i = tid; i < nt; i += kBinBlock) hist[i] = 0;
+            for (uint32_t i = tid; i < ((nt + 31u) & ~31u); i += kBinBlock) hist[i] = 0;
             __syncthreads();
             // count this chunk's entries per tile in LDS (at most kBinChunk
             // per tile: fits the 16-bit half)
@@ -514,7 +521,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                 if (s >= cnt) break;
                 const TileRange R = tile_range(sbox[surv_base + s], ts);
                 for (int ty = R.ty0; ty <= R.ty1; ++ty)
-                    for (int tx = R.tx0; tx <= R.tx1; ++tx) atomicAdd(&hist[(uint32_t)ty * tiles_x + (uint32_t)tx], 1u);
+                    for (int tx = R.tx0; tx <= R.tx1; ++tx) atomicAdd(&hist[swz((uint32_t)ty * tiles_x + (uint32_t)tx)], 1u);
             }
             __syncthreads();
             // one global operation per touched tile; a thread's tiles are
@@ -522,7 +529,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
             // together, not one tile after another
             if (!SCATTER) {
                 for (uint32_t i = tid; i < nt; i += kBinBlock) {
-                    const uint32_t c = hist[i] & 0xFFFFu;
+                    const uint32_t c = hist[swz(i)] & 0xFFFFu;
                     if (c) atomicAdd(&tile_count[tile_base + i], c);
                 }
             } else {
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) {
                     const uint32_t i = tid + (uint32_t)k * kBinBlock;
-                    c[k] = i < nt ? hist[i] & 0xFFFFu : 0u;
+                    c[k] = i < nt ? hist[swz(i)] & 0xFFFFu : 0u;
                     off[k] = i < nt ? tile_off[tile_base + i] : kOverflow;
                 }
 #pragma unroll
@@ -542,7 +549,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) {
                     const uint32_t i = tid + (uint32_t)k * kBinBlock;
-                    if (c[k]) lbase[i] = off[k] == kOverflow ? kOverflow : off[k] + got[k];
+                    if (c[k]) lbase[swz(i)] = off[k] == kOverflow ? kOverflow : off[k] + got[k];
                 }
             }
             if (SCATTER) {
@@ -556,9 +563,9 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                     for (int ty = R.ty0; ty <= R.ty1; ++ty)
                         for (int tx = R.tx0; tx <= R.tx1; ++tx) {
                             const uint32_t tl = (uint32_t)ty * tiles_x + (uint32_t)tx;
-                            const uint32_t b = lbase[tl];
+                            const uint32_t b = lbase[swz(tl)];
                             if (b == kOverflow) continue;
-                            const uint32_t rank = atomicAdd(&hist[tl], 1u << 16) >> 16;
+                            const uint32_t rank = atomicAdd(&hist[swz(tl)], 1u << 16) >> 16;
                             bins[bin_base + b + rank] = key;
                         }
                 }
