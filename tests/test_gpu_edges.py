@@ -88,3 +88,34 @@ def test_scene_without_triangles_and_view_of_nothing(ctx):
     assert ctx.get_error() == 0
     ctx.release(empty)
     ctx.release(one)
+
+
+def test_largest_batch(ctx):
+    """4,096 views in one launch sequence (the most one sequence holds: the
+    per-view prefix in setup's and binning's LDS is at its largest), 16 x 12
+    depth views: a sample against the oracle; 4,097 views are split into two
+    sequences, the last view checked too."""
+    import torch
+    import paper_1904_01201_amd as P
+    note("edges: 4096-view batch")
+    w = configs.room_2k_128()
+    sc = w.scenes[0]
+    h = ctx.upload_scene(sc)
+    sn = ctx.sensor(16, 12, 90.0, 0.01, P.OUT_DEPTH)
+    n = 4096
+    poses = w.poses[np.arange(n) % w.poses.shape[0], np.arange(n) % w.poses.shape[1]]
+    out = ctx.alloc(sn, n, tri=True)
+    items = [(h, sn, poses[k], None, out["depth"][k], out["tri"][k]) for k in range(n)]
+    ctx.render_batch(items)
+    torch.cuda.synchronize()
+    g = to_np(out)
+    for k in range(0, n, 257):
+        o = oracle.render_view(sc.positions, sc.colors, sc.indices, 16, 12, poses[k])
+        compare({"depth": g["depth"][k], "tri": g["tri"][k]}, o, f"view {k}")
+    extra = ctx.alloc(sn, 1, tri=True)
+    ctx.render_batch(items + [(h, sn, poses[5], None, extra["depth"], extra["tri"])])
+    torch.cuda.synchronize()
+    o = oracle.render_view(sc.positions, sc.colors, sc.indices, 16, 12, poses[5])
+    compare({k: v[0] for k, v in to_np(extra).items()}, o, "view 4096 (second sequence)")
+    assert ctx.get_error() == 0
+    ctx.release(h)
