@@ -28,19 +28,26 @@
  *     axis) in metres; colour is the perspective-correct interpolation of
  *     the vertex colours rounded to uint8;
  *   - no hit: depth 0, colour (0, 0, 0), triangle index HAB_NO_HIT.
+ * The same pass can also write the semantic instance mask, shade from a
+ * texture instead of the vertex colours, and add depth noise (see
+ * hab_mesh_desc and hab_sensor_desc); hab_actuate moves agents (turns and
+ * forward moves with collide-and-slide) and writes the camera poses that
+ * hab_stepper_step_device renders from.
  *
  * Memory: every output pointer is caller-owned device memory, contiguous,
- * row-major: rgb [N][H][W][3] uint8, depth [N][H][W] float, tri
- * [N][H][W] uint32.  The library never keeps an output pointer after the
- * call returns, except inside a stepper (which keeps the pointers it was
- * created with until it is destroyed).  Host arrays passed in are read
- * during the call only.
+ * row-major: rgb [N][H][W][3] uint8, depth [N][H][W] float, tri and
+ * semantic [N][H][W] uint32.  The library never keeps an output pointer
+ * after the call returns, except inside a stepper (which keeps the
+ * pointers it was created with until it is destroyed).  Host arrays passed
+ * in are read during the call only; device inputs (agent states, actions,
+ * device poses) are read when the enqueued work runs.
  *
  * Errors: every function returns a hab_status; nothing throws across the
  * boundary.  Argument errors are detected before any work is enqueued.
  * Rendering is asynchronous on the given HIP stream; a device-side fault
- * report (a vertex outside the fixed-point range, which validation makes
- * unreachable) is sticky and read with hab_get_error after synchronising.
+ * report (a vertex outside the fixed-point range: unreachable for poses
+ * checked on the host, possible for device poses) is sticky and read with
+ * hab_get_error after synchronising.
  *
  * Threading: a context is externally synchronised (one thread at a time);
  * scenes are immutable after upload and may be used by any stream.  Work
@@ -189,7 +196,8 @@ typedef struct {
 /* ---------------------------------------------------------- lifetime */
 /* Create a context on HIP device `device` (its ordinal). */
 hab_status hab_init(int device, hab_context **out);
-/* Synchronise and free everything the context owns (scenes included). */
+/* Synchronise and free everything the context owns (scenes and obstacle
+ * sets included). */
 hab_status hab_shutdown(hab_context *ctx);
 const char *hab_status_string(hab_status s);
 /* Sticky device-side error of this context (HAB_OK if none); call after
