@@ -88,6 +88,11 @@ def test_null_arguments(lib):
     assert lib.hab_render_batch(None, None, 0, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_stepper_step(None, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_profile_phases(None, 1) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_stepper_step_device(None, None, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_nav_upload(None, None, 0, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_nav_release(None, None) == B.HAB_ERR_INVALID_ARG
+    p = B.Actuation(0.1, 0.25, 1.0, 0.0)
+    assert lib.hab_actuate(None, None, 0, None, None, None, None, 1.5, C.byref(p), None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_server_submit(None, None, None) == B.HAB_ERR_INVALID_ARG
 
 
