@@ -898,8 +898,10 @@ __device__ __forceinline__ long long join64(int hi, int lo)
 // Colour, depth and index of the winning sub-triangle at pixel (i, j):
 // the winner's setup is rebuilt with colours, its three edge functions at
 // the pixel centre give the perspective-correct weights.
-__device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int j, uint32_t rgb[3],
-                                        float &depth)
+// Colour of the winner at pixel (i, j): the triangle's setup rebuilt with
+// the same arithmetic as the raster's (the depth comes from the winning
+// key's 1/w, the same value).
+__device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int j, uint32_t rgb[3])
 {
     const uint32_t t = key >> 1;
     const int sub = (int)(key & 1u);
@@ -926,7 +928,6 @@ __device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int
         // unreachable: the key came from a successful setup of the same
         // arithmetic; report it as a device fault rather than guess
         rgb[0] = rgb[1] = rgb[2] = 0;
-        depth = 0.0f;
         return false;
     }
     const long long px = 256ll * i + 128, py = 256ll * j + 128;
@@ -935,9 +936,6 @@ __device__ __forceinline__ bool resolve(const DView &v, uint32_t key, int i, int
     const long long E2 = edge_at(a.X, a.Y, b.X, b.Y, px, py);
     const float w0 = (float)E0 * a.rw, w1 = (float)E1 * b.rw, w2 = (float)E2 * c.rw;
     const float num = (w0 + w1) + w2;
-    const float invA = 1.0f / (float)A;
-    const float rho = num * invA;
-    depth = 1.0f / rho;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         float val = ((w0 * a.a[ch] + w1 * b.a[ch]) + w2 * c.a[ch]) / num;
@@ -979,7 +977,7 @@ __device__ __forceinline__ void tex_bilinear(const DView &v, float u, float t, u
 // resolve() for a textured scene: the same rebuild of the winner with the
 // texture coordinates as its two attributes.
 __device__ __forceinline__ bool resolve_tex(const DView &v, uint32_t key, int i, int j,
-                                            uint32_t rgb[3], float &depth)
+                                            uint32_t rgb[3])
 {
     const uint32_t t = key >> 1;
     const int sub = (int)(key & 1u);
@@ -1002,7 +1000,6 @@ __device__ __forceinline__ bool resolve_tex(const DView &v, uint32_t key, int i,
     bool rerr = false;
     if (!setup_sub(v, c0, c1, c2, sub, a, b, c, A, rerr)) {
         rgb[0] = rgb[1] = rgb[2] = 0;
-        depth = 0.0f;
         return false;
     }
     const long long px = 256ll * i + 128, py = 256ll * j + 128;
@@ -1011,8 +1008,6 @@ __device__ __forceinline__ bool resolve_tex(const DView &v, uint32_t key, int i,
     const long long E2 = edge_at(a.X, a.Y, b.X, b.Y, px, py);
     const float w0 = (float)E0 * a.rw, w1 = (float)E1 * b.rw, w2 = (float)E2 * c.rw;
     const float num = (w0 + w1) + w2;
-    const float invA = 1.0f / (float)A;
-    depth = 1.0f / (num * invA);
     const float u = ((w0 * a.a[0] + w1 * b.a[0]) + w2 * c.a[0]) / num;
     const float tv = ((w0 * a.a[1] + w1 * b.a[1]) + w2 * c.a[1]) / num;
     tex_bilinear(v, u, tv, rgb);
@@ -1317,14 +1312,12 @@ __global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ vi
     uint32_t rgb[3] = {0, 0, 0};
     float depth = 0.0f;
     if (best_key != kNone) {
-        if (!v.rgb) {
-            // no colour wanted: the depth is the reciprocal of the winning
-            // key's 1/w, the same value the rebuild would compute
-            depth = 1.0f / best_rho;
-        } else if (!(v.tex ? resolve_tex(v, best_key, pi, pj, rgb, depth)
-                           : resolve(v, best_key, pi, pj, rgb, depth))) {
+        // the depth is the reciprocal of the winning key's 1/w (the value a
+        // rebuild of the triangle would compute again); colour needs the
+        // rebuild
+        depth = 1.0f / best_rho;
+        if (v.rgb && !(v.tex ? resolve_tex(v, best_key, pi, pj, rgb) : resolve(v, best_key, pi, pj, rgb)))
             atomicOr(err, kErrResolve);
-        }
     }
     const size_t p = (size_t)pj * v.W + (size_t)pi;
     if (v.noise_sigma > 0.0f && best_key != kNone) {
