@@ -730,8 +730,15 @@ constexpr uint32_t kPacked = 1u << 25;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// Mask of the tile's 4x4-pixel quarters (row-major, TS/4 per row) that a
-// record's pixel box touches: 4, 16 or 64 bits.
+// The raster's lanes test their pixels block by block: an 8-pixel tile
+// (one wave) is cut into eight blocks of 4 columns x 2 rows, larger tiles
+// into 4x4-pixel quarters.  A record carries the mask of the tile's blocks
+// (row-major, NX per row) that its pixel box touches: 8, 16 or 64 bits.
+template <int TS>
+struct Blk {
+    static constexpr int WL = 2, HL = TS == 8 ? 1 : 2;   // log2 of the block's width, height
+    static constexpr int W = 1 << WL, H = 1 << HL, NX = TS / W, NY = TS / H;
+};
 template <int TS>
 using QMask = typename std::conditional<TS == 32, unsigned long long, uint32_t>::type;
 
@@ -777,14 +784,14 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     const int bi0 = max(pb.i0 - ti0, 0), bi1 = min(pb.i1 - ti0, TS - 1);
     const int bj0 = max(pb.j0 - tj0, 0), bj1 = min(pb.j1 - tj0, TS - 1);
     if (bi0 > bi1 || bj0 > bj1) return false;
-    constexpr int NQ = TS / 4;
+    using B = Blk<TS>;
     using Q = QMask<TS>;
-    const int qx0 = bi0 >> 2, qx1 = bi1 >> 2, qy0 = bj0 >> 2, qy1 = bj1 >> 2;
+    const int qx0 = bi0 >> B::WL, qx1 = bi1 >> B::WL, qy0 = bj0 >> B::HL, qy1 = bj1 >> B::HL;
     const Q row = (Q)(((Q)2 << qx1) - ((Q)1 << qx0));
     qm = 0;
 #pragma unroll
-    for (int qy = 0; qy < NQ; ++qy)
-        if (qy >= qy0 && qy <= qy1) qm |= row << (qy * NQ);
+    for (int qy = 0; qy < B::NY; ++qy)
+        if (qy >= qy0 && qy <= qy1) qm |= row << (qy * B::NX);
 
     // edge k runs from vertex k+1 to vertex k+2
     const int dx[3] = {c.X - b.X, a.X - c.X, b.X - a.X};
@@ -854,25 +861,38 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     x.ny1 = -dy[1];
     x.ny2 = -dy[2];
     if constexpr (TS == 8) {
-        // Drop the quarters that hold no pixel centre the triangle can
-        // cover: an edge whose largest value over a quarter's centres is
-        // below its threshold (1 if not owned, else 0) excludes the quarter.
-        // Exact in int32 for packed records (|E| < 2^31 over the tile).
+        // Drop the blocks that hold no pixel centre the triangle can cover:
+        // an edge whose largest value over a block's centres is below its
+        // threshold (1 if not owned, else 0) excludes the block.  E_k peaks
+        // at the block corner that dx_k and -dy_k favour; g_k is that peak
+        // for block (0, 0) less the threshold, and moves by dx_k 256 H per
+        // block row and by -dy_k 256 W per block column.  A block stays
+        // while every such value is >= 0, i.e. while the sign bit of their
+        // OR is clear.  Every value is E_k at a pixel centre of the tile,
+        // minus 0 or 1: exact in int32 for packed records (|E| < 2^31).
         if (packed) {
+            constexpr int PW = 256 * (B::W - 1), QH = 256 * (B::H - 1);
+            int g[3], sp[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                g[k] = clo[k] + (dx[k] > 0 ? __mul24(dx[k], QH) : 0) - (dy[k] < 0 ? __mul24(dy[k], PW) : 0) -
+                       (int)((notown >> (8 * k)) & 1u);
+                sp[k] = dy[k] * (256 * B::W);
+            }
             QMask<TS> keep = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int P0 = 256 * 4 * (q & 1), Q0 = 256 * 4 * (q >> 1);
-                bool ok = (qm >> q) & 1u;
+            for (int qy = 0; qy < B::NY; ++qy) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int emax = clo[k] + __mul24(dx[k], dx[k] > 0 ? Q0 + 768 : Q0) -
-                                     __mul24(dy[k], dy[k] < 0 ? P0 + 768 : P0);
-                    ok = ok && emax >= (int)((notown >> (8 * k)) & 1u);
+                for (int qx = 0; qx < B::NX; ++qx) {
+                    const int e = (g[0] - qx * sp[0]) | (g[1] - qx * sp[1]) | (g[2] - qx * sp[2]);
+                    keep |= (QMask<TS>)((uint32_t)~e >> 31) << (qy * B::NX + qx);
                 }
-                if (ok) keep |= 1u << q;
+                if (qy + 1 < B::NY) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) g[k] += dx[k] * (256 * B::H);
+                }
             }
-            qm = keep;
+            qm &= keep;
             if (!qm) return false;
         }
     }
@@ -1033,19 +1053,21 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     constexpr int NS = TS / 8;
     constexpr uint32_t cls = TS == 8 ? 0u : TS == 16 ? 1u : 2u;
     constexpr uint32_t S = kSegPerTile * NT;
-    constexpr int NQ = TS / 4;
+    using B = Blk<TS>;
+    // a wave's 8x8 pixels hold NL blocks: 2 columns of 8 / H rows
+    constexpr int NL = 2 * (8 / B::H);
     using QM = QMask<TS>;
     __shared__ LRec srec[NT];
     __shared__ LExt sext[NT];
     __shared__ QM sqm[NT];
-    // per wave and quarter: byte offsets in srec of the chunk's records that
-    // touch the quarter (zeroed once, so a stale entry is still a record)
-    __shared__ uint16_t slist[NT / 64][4][64];
+    // per wave and block: byte offsets in srec of the chunk's records that
+    // touch the block (zeroed once, so a stale entry is still a record)
+    __shared__ uint16_t slist[NT / 64][NL][64];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const unsigned long long lt = lanemask_lt();
-    for (uint32_t i = lane; i < 4 * 64; i += 64) (&slist[wave][0][0])[i] = 0;
+    for (uint32_t i = lane; i < NL * 64; i += 64) (&slist[wave][0][0])[i] = 0;
     const int sx = (int)(wave % NS), sy = (int)(wave / NS);
     const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
     const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
@@ -1123,12 +1145,12 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             const uint32_t m = min((uint32_t)NT, end - base);
             // z-test of this lane's pixel against fragment weights w_k where
             // covered (cov) and the wave's coverage ballot cm
-            auto zkeep = [&](const LRec &R, bool cov, unsigned long long cm, float w0, float w1, float w2) {
+            auto zkeep = [&](const LRec &R, bool cov, float w0, float w1, float w2) {
                 const float num = (w0 + w1) + w2;
                 const float rho = num * R.invA;
                 const unsigned long long cand =
                     ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
-                if (count) ncov += (uint32_t)__popcll(cm & inmask);
+                if (count) ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
                 best = (cov && cand > best) ? cand : best;
             };
             // one step: every active lane tests its pixel against record R
@@ -1143,9 +1165,8 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
                     const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
                     const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
-                    const unsigned long long cm = __ballot(cov);
-                    if (!cm) return;
-                    zkeep(R, cov, cm, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
+                    if (!__ballot(cov)) return;
+                    zkeep(R, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
                     return;
                 }
                 bool cov = false;
@@ -1177,41 +1198,45 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     w1 = (float)E1 * R.rw1;
                     w2 = (float)E2 * R.rw2;
                 }
-                const unsigned long long cm = __ballot(cov);
-                if (!cm) return;
-                zkeep(R, cov, cm, w0, w1, w2);
+                if (!__ballot(cov)) return;
+                zkeep(R, cov, w0, w1, w2);
             };
-            // the wave's four 16-lane quarters (4x4 pixels each) walk their
-            // own lists of records whose box touches them: one step tests up
-            // to four records.  Bits qb, qb+1, qb+NQ, qb+NQ+1 of a record's
-            // quarter mask are this wave's quarters.
-            // Per chunk of 64 records, each quarter's relevant records are
-            // compacted into its LDS list; step i then tests entry i of every
-            // quarter's list.
-            const uint32_t qb = (uint32_t)(2 * sy * NQ + 2 * sx);
-            const uint32_t lq = ((lane >> 5) << 1) | ((lane >> 2) & 1u);
+            // the wave's NL blocks (8 or 16 lanes each) walk their own lists
+            // of records whose box touches them: one step tests up to NL
+            // records.  Block b of this wave is bit qb + (b / 2) NX + b % 2
+            // of a record's block mask.  Per chunk of 64 records, each
+            // block's relevant records are compacted into its LDS list; step
+            // i then tests entry i of every block's list.
+            const uint32_t qb = (uint32_t)(sy * (8 / B::H) * B::NX + 2 * sx);
+            const uint32_t lq = ((lane >> (3 + B::HL)) << 1) | ((lane >> 2) & 1u);
             uint16_t *const wl = &slist[wave][0][0];
             for (uint32_t g = 0; g < m; g += 64) {
                 const bool in = g + lane < m;
                 const QM qm = in ? sqm[g + lane] : (QM)0;
-                const bool r0 = (qm >> qb) & 1u, r1 = (qm >> (qb + 1)) & 1u;
-                const bool r2 = (qm >> (qb + NQ)) & 1u, r3 = (qm >> (qb + NQ + 1)) & 1u;
-                const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
-                const unsigned long long m2 = __ballot(r2), m3 = __ballot(r3);
-                if (!(m0 | m1 | m2 | m3)) continue;
+                bool rl[NL];
+                unsigned long long mk[NL], any = 0;
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    rl[b] = (qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u;
+                    mk[b] = __ballot(rl[b]);
+                    any |= mk[b];
+                }
+                if (!any) continue;
                 const uint16_t off = (uint16_t)((g + lane) * sizeof(LRec));
-                if (r0) wl[0 * 64 + __popcll(m0 & lt)] = off;
-                if (r1) wl[1 * 64 + __popcll(m1 & lt)] = off;
-                if (r2) wl[2 * 64 + __popcll(m2 & lt)] = off;
-                if (r3) wl[3 * 64 + __popcll(m3 & lt)] = off;
+                bool rel = false;
+                uint32_t nsteps = 0, myc = 0;
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    if (rl[b]) wl[b * 64 + __popcll(mk[b] & lt)] = off;
+                    rel = rel || rl[b];
+                    const uint32_t c = (uint32_t)__popcll(mk[b]);
+                    nsteps = max(nsteps, c);
+                    myc = lq == (uint32_t)b ? c : myc;
+                }
+                nsteps = uniform(nsteps);
                 // does every record this wave will test have the packed form?
-                const bool rel = r0 || r1 || r2 || r3;
                 const bool allpk = !__ballot(rel && !(srec[g + lane].flags & kPacked));
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
-                const uint32_t c2 = (uint32_t)__popcll(m2), c3 = (uint32_t)__popcll(m3);
-                const uint32_t nsteps = uniform(max(max(c0, c1), max(c2, c3)));
-                const uint32_t myc = lq == 0 ? c0 : lq == 1 ? c1 : lq == 2 ? c2 : c3;
                 const uint16_t *const myl = wl + lq * 64;
                 const char *const rb = reinterpret_cast<const char *>(srec);
                 if (allpk) {
