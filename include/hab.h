@@ -384,6 +384,19 @@ hab_status hab_profile_phases(hab_context *ctx, uint32_t phase_mask);
 /* Synchronise, add up every timed sequence since the last read, reset. */
 hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out);
 
+/* ---------------------------------------------------------- self-check */
+/* The setup and raster take 1/w at the snap and 1/A of a triangle's twice
+ * area with a reciprocal-and-Newton-step sequence instead of a division;
+ * it must return the IEEE quotient (what a division gives) bit for bit.
+ * This counts the positive floats x whose bit patterns lie in
+ * [lo_bits, hi_bits) for which it does not, on ctx's device and `stream`
+ * (synchronised before returning), into *mismatches.  Requires
+ * lo_bits < hi_bits <= 0x7F800000, else HAB_ERR_INVALID_ARG.  The range the
+ * sequence serves, [0x00800000, 0x7E800000) (2^-126 to 2^126; other inputs
+ * take the division), is about 2.1e9 values and a fraction of a second. */
+hab_status hab_selfcheck_reciprocal(hab_context *ctx, uint32_t lo_bits, uint32_t hi_bits,
+                                    hipStream_t stream, uint64_t *mismatches);
+
 /* ---------------------------------------------------------- autotune */
 /* Pick a tile size (8, 16, 32) and bin capacity factor (1, 2, 4) for every
  * batch class (scene-size bucket, resolution bucket, output mix) of a

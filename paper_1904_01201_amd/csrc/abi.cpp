@@ -406,4 +406,25 @@ hab_status hab_profile_read(hab_context *ctx, hab_phase_times *out)
     });
 }
 
+hab_status hab_selfcheck_reciprocal(hab_context *ctx, uint32_t lo_bits, uint32_t hi_bits, hipStream_t stream,
+                                    uint64_t *mismatches)
+{
+    if (!ctx || !mismatches || lo_bits >= hi_bits || hi_bits > 0x7F800000u) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        unsigned long long *d = nullptr;
+        HAB_HIP(hipMalloc(&d, sizeof *d));
+        unsigned long long h = 0;
+        hipError_t e = hipMemsetAsync(d, 0, sizeof *d, stream);
+        if (e == hipSuccess) e = launch_check_recip(lo_bits, hi_bits, d, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        (void)hipFree(d);
+        if (e != hipSuccess) return HAB_ERR_DEVICE;
+        *mismatches = h;
+        return HAB_OK;
+    });
+}
+
 }  // extern "C"

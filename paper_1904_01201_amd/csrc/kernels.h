@@ -61,4 +61,9 @@ int raster_blocks_per_cu(int ts);
 // Enqueue the whole sequence on stream s.
 hipError_t launch_render(const LaunchPlan &L, hipStream_t s);
 
+// Compare recip_rn with the IEEE division 1/x for every float whose bits
+// lie in [lo, hi) (lo < hi <= 0x7F800000), adding the number of differing
+// results to *count (device memory, one 64-bit word), on stream s.
+hipError_t launch_check_recip(uint32_t lo, uint32_t hi, unsigned long long *count, hipStream_t s);
+
 }  // namespace habmi

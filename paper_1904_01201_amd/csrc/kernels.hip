@@ -901,7 +901,7 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
     float fA;
     if (A == (long long)(int)A) fA = (float)(int)A;
     else fA = (float)A;
-    r.invA = 1.0f / fA;
+    r.invA = recip_rn(fA);
     r.rw0 = a.rw;
     r.rw1 = b.rw;
     r.rw2 = c.rw;
@@ -1447,6 +1447,26 @@ hipError_t launch_render(const LaunchPlan &L, hipStream_t s)
         }
     }
     mark(L, 2 * kPhaseResolve + 1, s);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ self-check
+__global__ __launch_bounds__(256) void k_check_recip(uint32_t lo, uint32_t hi, unsigned long long *count)
+{
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    uint32_t bad = 0;
+    for (unsigned long long b = lo + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; b < hi; b += stride) {
+        const float x = __uint_as_float((uint32_t)b);
+        bad += __float_as_uint(recip_rn(x)) != __float_as_uint(1.0f / x) ? 1u : 0u;
+    }
+    const uint32_t tot = wave_sum_u32(bad);
+    if (lane_id() == 0 && tot) atomicAdd(count, (unsigned long long)tot);
+}
+
+hipError_t launch_check_recip(uint32_t lo, uint32_t hi, unsigned long long *count, hipStream_t s)
+{
+    if (!count || lo >= hi || hi > 0x7F800000u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_check_recip, dim3(2048), dim3(256), 0, s, lo, hi, count);
     return hipGetLastError();
 }
 

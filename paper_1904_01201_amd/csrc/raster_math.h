@@ -23,6 +23,22 @@ namespace habmi {
 
 constexpr float kDomain = 536870912.0f;   // 2^29: |X|, |Y| bound in 1/256 px
 
+// Correctly rounded 1/x, the value of the IEEE division.  For x in
+// [2^-126, 2^126) the hardware reciprocal (within one ulp) refined by one
+// Newton step, e = 1 - x y exact in a fused multiply-add and y + e y
+// rounded once, gives that value (checked for every float of the range by
+// launch_check_recip); elsewhere the division itself.
+constexpr uint32_t kRecipLo = 0x00800000u;   // 2^-126
+constexpr uint32_t kRecipHi = 0x7E800000u;   // 2^126
+__device__ __forceinline__ float recip_rn(float x)
+{
+    if (__builtin_expect(__float_as_uint(x) - kRecipLo < kRecipHi - kRecipLo, 1)) {
+        const float y = __builtin_amdgcn_rcpf(x);
+        return __builtin_fmaf(__builtin_fmaf(-x, y, 1.0f), y, y);
+    }
+    return 1.0f / x;
+}
+
 // Camera-space vertex with NA interpolated attributes (colour channels).
 template <int NA>
 struct Vtx {
@@ -95,7 +111,7 @@ __device__ __forceinline__ int clip_poly(const Vtx<NA> &v0, const Vtx<NA> &v1, c
 template <int NA>
 __device__ __forceinline__ bool snap(const DView &v, const Vtx<NA> &c, SVtx<NA> &s)
 {
-    float rw = 1.0f / c.w;
+    float rw = recip_rn(c.w);
     float xs = rintf(v.cxS + (c.x * v.fS) * rw);
     float ys = rintf(v.cyS - (c.y * v.fS) * rw);
     bool ok = fabsf(xs) < kDomain && fabsf(ys) < kDomain;

@@ -291,6 +291,15 @@ class Context:
         return {name: {"ms": t.ms[k], "launches": int(t.launches[k])}
                 for k, name in enumerate(B.PHASES) if t.launches[k]}
 
+    # ------------------------------------------------------------ self-check
+    def selfcheck_reciprocal(self, lo_bits: int = 0x00800000, hi_bits: int = 0x7E800000, stream=None) -> int:
+        """Floats with bits in [lo_bits, hi_bits) whose reciprocal, as the
+        setup and raster take it, differs from the IEEE quotient 1/x."""
+        n = C.c_uint64()
+        B.check(self.lib.hab_selfcheck_reciprocal(self.h, lo_bits, hi_bits, _stream_ptr(stream), C.byref(n)),
+                "hab_selfcheck_reciprocal")
+        return int(n.value)
+
     # ------------------------------------------------------------ actuation
     def nav_upload(self, segments) -> "NavHandle":
         """Obstacle segments [n, 4] float32 (x0, z0, x1, z1) of one scene."""

@@ -94,6 +94,8 @@ def test_null_arguments(lib):
     p = B.Actuation(0.1, 0.25, 1.0, 0.0)
     assert lib.hab_actuate(None, None, 0, None, None, None, None, 1.5, C.byref(p), None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_server_submit(None, None, None) == B.HAB_ERR_INVALID_ARG
+    n = C.c_uint64()
+    assert lib.hab_selfcheck_reciprocal(None, 0x00800000, 0x7E800000, None, C.byref(n)) == B.HAB_ERR_INVALID_ARG
 
 
 def test_output_tensor_checks():
