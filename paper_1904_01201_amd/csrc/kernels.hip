@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     __shared__ QM sqm[NT];
     // per wave and block: byte offsets in srec of the chunk's records that
     // touch the block (zeroed once, so a stale entry is still a record)
-    __shared__ uint16_t slist[NT / 64][NL][64];
+    __shared__ __align__(8) uint32_t slist[NT / 64][NL][64];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -1209,7 +1209,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             // i then tests entry i of every block's list.
             const uint32_t qb = (uint32_t)(sy * (8 / B::H) * B::NX + 2 * sx);
             const uint32_t lq = ((lane >> (3 + B::HL)) << 1) | ((lane >> 2) & 1u);
-            uint16_t *const wl = &slist[wave][0][0];
+            uint32_t *const wl = &slist[wave][0][0];
             for (uint32_t g = 0; g < m; g += 64) {
                 const bool in = g + lane < m;
                 const QM qm = in ? sqm[g + lane] : (QM)0;
@@ -1222,7 +1222,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     any |= mk[b];
                 }
                 if (!any) continue;
-                const uint16_t off = (uint16_t)((g + lane) * sizeof(LRec));
+                const uint32_t off = (g + lane) * (uint32_t)sizeof(LRec);
                 bool rel = false;
                 uint32_t nsteps = 0, myc = 0;
 #pragma unroll
@@ -1237,10 +1237,17 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                 // does every record this wave will test have the packed form?
                 const bool allpk = !__ballot(rel && !(srec[g + lane].flags & kPacked));
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                const uint16_t *const myl = wl + lq * 64;
+                const uint32_t *const myl = wl + lq * 64;
                 const char *const rb = reinterpret_cast<const char *>(srec);
                 if (allpk) {
-                    for (uint32_t i = 0; i < nsteps; ++i) {
+                    // two steps per list read (one 8-byte LDS load)
+                    uint32_t i = 0;
+                    for (; i + 1 < nsteps; i += 2) {
+                        const uint2 o2 = *reinterpret_cast<const uint2 *>(myl + i);
+                        visit(lds_rec_at(rb, o2.x), o2.x / (uint32_t)sizeof(LRec), i < myc, std::true_type());
+                        visit(lds_rec_at(rb, o2.y), o2.y / (uint32_t)sizeof(LRec), i + 1 < myc, std::true_type());
+                    }
+                    if (i < nsteps) {
                         const uint32_t o = myl[i];
                         visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::true_type());
                     }
