@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                 best = (cov && cand > best) ? cand : best;
             };
             // one step: every active lane tests its pixel against record R
-            // (index k) of its quarter under the top-left rule (an edge not
+            // (index k) of its block under the top-left rule (an edge not
             // owned needs E > 0)
             auto visit = [&](const LRec &R, uint32_t k, bool act, auto allpk) {
                 const uint32_t fl = R.flags;
