@@ -334,17 +334,20 @@ def main():
     # ---------------------------------------------------- env loop
     # the whole environment step on the device: actuation of the 64 agents
     # (random actions, collide-and-slide) feeding the captured render step
-    from scenegen import agents_from_states, nav_segments, poses_from_agents
+    from scenegen import agents_from_states, nav_segments
     from scenegen.walks import random_free_states
     navs_h = [ctx.nav_upload(nav_segments(s)) for s in w.scenes]
     ag_np = np.concatenate([agents_from_states(*random_free_states(w.scenes[w.env_scene[e]], 1, seed=900 + e))
                             for e in range(E)])
     ag = torch.from_numpy(ag_np).cuda()
-    env_poses = torch.from_numpy(poses_from_agents(ag_np)).cuda()
+    env_poses = torch.empty((E, 12), dtype=torch.float32, device="cuda")
     nav_of = ctx.nav_array([navs_h[w.env_scene[e]] for e in range(E)])
+    # a stop action writes the starting camera poses (the library's own mapping)
+    ctx.actuate(nav_of, ag, torch.zeros(E, dtype=torch.uint8, device="cuda"), None, env_poses)
+    start_poses = env_poses.cpu().numpy()
     acts = torch.from_numpy(np.random.default_rng(4).choice([1, 1, 2, 3], size=(a.steps + a.warmup, E))
                             .astype(np.uint8)).cuda()
-    st = ctx.stepper([(hs[w.env_scene[e]], sensor, poses_from_agents(ag_np[e:e + 1])[0], rgb[e], depth[e], None)
+    st = ctx.stepper([(hs[w.env_scene[e]], sensor, start_poses[e], rgb[e], depth[e], None)
                       for e in range(E)], tile_size=a.tile_size)
     for s in range(a.warmup):
         ctx.actuate(nav_of, ag, acts[s], None, env_poses)

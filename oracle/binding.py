@@ -91,6 +91,8 @@ def _load():
             lib.or_actuate.restype = C.c_int
             lib.or_actuate.argtypes = [f32p, C.c_uint32, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_uint32, C.POINTER(Agent), u32p]
+            lib.or_agent_pose.restype = None
+            lib.or_agent_pose.argtypes = [C.POINTER(Agent), C.c_float, f32p]
             lib.or_depth_noise.restype = C.c_int
             lib.or_depth_noise.argtypes = [f32p, u32p, C.c_uint32, C.c_uint32, C.c_double,
                                            C.c_uint64, f64p, f64p]
@@ -283,3 +285,18 @@ def actuate(segments, agents, actions, radius, step, turn_cos, turn_sin):
         out[k] = (a.x, a.z, a.fx, a.fz)
         hit[k] = bool(flag.value)
     return out, hit
+
+
+def agent_pose(agents, height):
+    """float32 [N, 12] camera poses (position, row-major world-from-camera
+    rotation) of agent states [N, 4] f64 (x, z, fx, fz), the sensor at
+    ``height`` above the floor."""
+    ag = np.ascontiguousarray(agents, np.float64).reshape(-1, 4)
+    out = np.empty((ag.shape[0], 12), np.float32)
+    lib = _load()
+    buf = (C.c_float * 12)()
+    for k in range(ag.shape[0]):
+        a = Agent(*ag[k])
+        lib.or_agent_pose(C.byref(a), C.c_float(height), buf)
+        out[k] = np.frombuffer(buf, np.float32)
+    return out

@@ -759,3 +759,24 @@ int or_actuate(const float *seg, uint32_t nseg, double radius, double step, doub
     ag->z = pz;
     return OR_OK;
 }
+
+/* Camera pose of an agent state (Sec. 4 "Sensory input": the sensor sits at
+ * a fixed height above the agent's base and faces the way the agent does).
+ * The camera looks along its -Z axis with +Y up, so its axes in the world
+ * are right = (-fz, 0, fx), up = (0, 1, 0) and back = (-fx, 0, -fz), the
+ * columns of the row-major world-from-camera rotation.  Each entry is the
+ * fp64 value rounded once to fp32; no trigonometry is involved. */
+void or_agent_pose(const or_agent *ag, float height, float pose[12])
+{
+    const double right[3] = {-ag->fz, 0.0, ag->fx};
+    const double up[3] = {0.0, 1.0, 0.0};
+    const double back[3] = {-ag->fx, 0.0, -ag->fz};
+    pose[0] = (float)ag->x;
+    pose[1] = height;
+    pose[2] = (float)ag->z;
+    for (int r = 0; r < 3; ++r) {
+        pose[3 + 3 * r + 0] = (float)right[r];
+        pose[3 + 3 * r + 1] = (float)up[r];
+        pose[3 + 3 * r + 2] = (float)back[r];
+    }
+}

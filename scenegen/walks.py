@@ -160,17 +160,3 @@ def agents_from_states(x, z, yaw) -> np.ndarray:
     yaw = np.asarray(yaw, np.float64)
     return np.stack([np.asarray(x, np.float64), np.asarray(z, np.float64),
                      -np.sin(yaw), -np.cos(yaw)], axis=1)
-
-
-def poses_from_agents(agents, y=SENSOR_HEIGHT) -> np.ndarray:
-    """float32 [n, 12] camera poses of agent states (no trigonometry: the
-    rotation's columns are the camera's right (-fz, 0, fx), up and back
-    (-fx, 0, -fz) vectors)."""
-    a = np.asarray(agents, np.float64).reshape(-1, 4)
-    fx, fz = a[:, 2], a[:, 3]
-    zero, one = np.zeros_like(fx), np.ones_like(fx)
-    out = np.stack([a[:, 0], np.full_like(fx, y), a[:, 1],
-                    -fz, zero, -fx,
-                    zero, one, zero,
-                    fx, zero, -fz], axis=1)
-    return out.astype(np.float32)

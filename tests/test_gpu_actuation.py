@@ -3,7 +3,7 @@
 Bar: agent states (fp64 position and forward vector) and collision flags
 bit-identical to the oracle's (the same fp64 operation sequence, IEEE
 division and square root on both sides); camera poses equal to the
-trig-free poses of those states.  Covered: the closed-form cases, a
+oracle's camera poses of those states.  Covered: the closed-form cases, a
 2,048-agent walk over two apartments with interleaved scenes, the
 4 x 1,024-agent walk over the benchmark's four apartments, a scene with no
 obstacles, action values above 3, and argument errors.
@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from scenegen import (AGENT_RADIUS, FORWARD_M, TURN_DEG, agents_from_states, configs,
-                      make_apartment, nav_segments, poses_from_agents)
+                      make_apartment, nav_segments)
 from scenegen.walks import random_free_states
 from tests.gpu_common import gpu_ctx, note
 
@@ -69,7 +69,7 @@ def test_closed_form_cases(ctx):
                                AGENT_RADIUS, FORWARD_M, C10, S10)
         assert np.array_equal(g[k], o[0]), (k, g[k], o[0])
         assert gh[k] == oh[0], k
-    assert np.array_equal(gp, poses_from_agents(g))
+    assert np.array_equal(gp, oracle.agent_pose(g, 1.5))
     for nv in navs:
         ctx.nav_release(nv)
 
@@ -95,7 +95,7 @@ def walk(ctx, scenes, n_per, steps, seed):
         bad = ~(g == o).all(axis=1)
         assert not bad.any(), (step, int(bad.sum()), np.argwhere(bad)[:3].ravel().tolist())
         assert np.array_equal(gh, oh), step
-        assert np.array_equal(gp, poses_from_agents(g)), step
+        assert np.array_equal(gp, oracle.agent_pose(g, 1.5)), step
         hits += int(gh.sum())
         agents = g
     for nv in navs_h:
@@ -171,7 +171,7 @@ def test_device_resident_env_loop(ctx):
         agents[owner == i] = parts[i]
     sn = ctx.sensor(128, 96, 90.0, 0.01, depth_noise_sigma=0.05)
     outs = [ctx.alloc(sn, 1, tri=True) for _ in range(16)]
-    poses0 = poses_from_agents(agents)
+    poses0 = oracle.agent_pose(agents, 1.5)
     items = [(hs[owner[e]], sn, poses0[e], outs[e]["rgb"], outs[e]["depth"], outs[e]["tri"], None, 10 * e)
              for e in range(16)]
     st = ctx.stepper(items)

@@ -143,3 +143,68 @@ def test_invariants_on_an_apartment(oracle_lib):
         collided_total += int(hit.sum())
         ag = new
     assert collided_total > 200          # the walk meets walls and boxes often
+
+
+# --------------------------------------------------------------- camera pose of an agent
+# Sec. 4 "Sensory input": the sensor sits 1.5 m above the agent's base and
+# faces the agent's heading.  The expected values below come from the camera
+# convention (the camera looks along its -Z axis, +Y up, +X right) and the
+# projection pins of the renderer, not from the pose function itself.
+HEIGHT = 1.5
+
+
+def test_pose_at_yaw_zero_is_the_identity(oracle_lib):
+    """Heading (0, -1) is yaw 0, the camera's own -Z: rotation I, position
+    (x, height, z)."""
+    p = oracle_lib.agent_pose([[0.75, -2.5, 0.0, -1.0]], HEIGHT)[0]
+    assert np.array_equal(p[:3], np.float32([0.75, HEIGHT, -2.5]))
+    assert np.array_equal(p[3:].reshape(3, 3), np.eye(3, dtype=np.float32))
+
+
+def test_pose_matches_the_yaw_rotation(oracle_lib):
+    """For heading (-sin y, -cos y) the rotation is the yaw rotation about +Y,
+    [[cos, 0, sin], [0, 1, 0], [-sin, 0, cos]], within one fp32 rounding."""
+    yaw = np.linspace(0.0, 2.0 * np.pi, 73)
+    ag = np.stack([np.zeros_like(yaw), np.zeros_like(yaw), -np.sin(yaw), -np.cos(yaw)], 1)
+    p = oracle_lib.agent_pose(ag, HEIGHT).astype(np.float64)
+    c, s = np.cos(yaw), np.sin(yaw)
+    R = np.stack([c, 0 * c, s, 0 * c, 1 + 0 * c, 0 * c, -s, 0 * c, c], 1)
+    assert np.abs(p[:, 3:] - R).max() <= 2.0 ** -24
+    # orthonormal, right-handed
+    Rm = p[:, 3:].reshape(-1, 3, 3)
+    assert np.abs(np.einsum("nij,nik->njk", Rm, Rm) - np.eye(3)).max() < 1e-6
+    assert np.abs(np.linalg.det(Rm) - 1.0).max() < 1e-6
+
+
+def test_pose_looks_along_the_heading(oracle_lib):
+    """A point 2 m ahead of the agent at sensor height projects to the
+    principal point (64, 64) of a 128^2, 90 degree sensor (X = Y = 16384);
+    a point 2 m ahead and 0.5 m to the agent's right (heading turned 90
+    degrees clockwise seen from above: (-fz, fx)) lands at x = 64 + 64 *
+    0.5 / 2 = 80 px; a point 0.5 m higher lands at y = 48 px (rows grow
+    downwards).  A transposed rotation or a mirrored right vector moves
+    them."""
+    rng = np.random.default_rng(7)
+    for yaw in rng.uniform(0.0, 2.0 * np.pi, 12):
+        fx, fz = -math.sin(yaw), -math.cos(yaw)
+        x, z = rng.uniform(-3, 3), rng.uniform(-3, 3)
+        pose = oracle_lib.agent_pose([[x, z, fx, fz]], HEIGHT)[0]
+        ahead = [x + 2 * fx, HEIGHT, z + 2 * fz]
+        X, Y, _ = oracle_lib.project_point(ahead, pose, 128, 128)
+        assert abs(X - 16384) <= 2 and abs(Y - 16384) <= 2, (yaw, X, Y)
+        right = [x + 2 * fx - 0.5 * fz, HEIGHT, z + 2 * fz + 0.5 * fx]
+        X, Y, _ = oracle_lib.project_point(right, pose, 128, 128)
+        assert abs(X - 80 * 256) <= 2 and abs(Y - 16384) <= 2, (yaw, X, Y)
+        up = [x + 2 * fx, HEIGHT + 0.5, z + 2 * fz]
+        X, Y, _ = oracle_lib.project_point(up, pose, 128, 128)
+        assert abs(X - 16384) <= 2 and abs(Y - 48 * 256) <= 2, (yaw, X, Y)
+
+
+def test_pose_after_36_left_turns_returns(oracle_lib):
+    """36 turns of 10 degrees are a full circle: the pose returns to the
+    start within the fp64 turn error (far below one fp32 rounding of 1)."""
+    ag = np.array([[1.0, 2.0, 0.0, -1.0]])
+    p0 = oracle_lib.agent_pose(ag, HEIGHT)
+    for _ in range(36):
+        ag, _ = act(oracle_lib, np.zeros((0, 4)), ag, [2])
+    assert np.abs(oracle_lib.agent_pose(ag, HEIGHT) - p0).max() < 1e-6

@@ -345,3 +345,100 @@ def test_tiny_fronto_parallel_triangles_exact_depth(oracle_lib):
     hit = r["tri"] != NONE
     assert hit.sum() > 200
     assert ulp_diff(r["depth"][hit], np.float32(2.5)).max() <= 6
+
+
+# --------------------------------------------------------------- work counters
+# The per-view counters are the algorithmic work the benchmark's roofline
+# figure is built from (Sec. 3 "Performance": cost grows with the number of
+# triangles drawn and the pixels they cover).  survivors = sub-triangles with
+# a non-empty box of pixel centres in the viewport, bbox_tests = the number
+# of those centres, covered = (sub-triangle, pixel) pairs that pass the
+# coverage test, whether or not they win the depth test.
+def corner(x, y, w=1.0):
+    """Camera point at depth w that projects to the pixel corner (x, y) px
+    of a 128^2, 90 degree sensor (f = 64)."""
+    return [(x - 64) * w / 64.0, -(y - 64) * w / 64.0, -w]
+
+
+def stats_of(oracle_lib, pos, idx, W=128):
+    return oracle_lib.render_view(pos, None, idx, W, W, IDENT_POSE)["stats"]
+
+
+def test_counters_square_on_pixel_corners(oracle_lib):
+    """A square with corners on the pixel corners (10, 30) and (20, 40): each
+    half's box of centres is columns 10..19 x rows 30..39 (a centre i + 1/2
+    lies inside [10, 20] for i = 10..19), 100 each; the two halves cover
+    each of the 100 pixels exactly once."""
+    pos, idx = quad(corner(10, 30), corner(20, 30), corner(20, 40), corner(10, 40))
+    st = stats_of(oracle_lib, pos, idx)
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (2, 200, 100)
+
+
+def test_counters_right_triangle_on_centres(oracle_lib):
+    """Legs on pixel centres: vertices at the centres of (20, 20), (20 + n,
+    20) and (20, 20 + n).  Its box holds (n + 1)^2 centres; under the
+    top-left rule the top and left legs are owned and the hypotenuse is
+    not, so exactly the centres (20 + u, 20 + v) with u, v >= 0, u + v < n
+    are covered: n (n + 1) / 2."""
+    for n in (1, 2, 5, 13):
+        pos = np.array([centre(20, 20), centre(20 + n, 20), centre(20, 20 + n)], np.float32)
+        idx = np.array([[0, 1, 2]], np.uint32)
+        st = stats_of(oracle_lib, pos, idx)
+        assert (st["survivors"], st["bbox_tests"], st["covered"]) == (1, (n + 1) ** 2, n * (n + 1) // 2), n
+        # the other winding gives the same counts
+        st = stats_of(oracle_lib, pos, idx[:, [0, 2, 1]])
+        assert (st["bbox_tests"], st["covered"]) == ((n + 1) ** 2, n * (n + 1) // 2), n
+
+
+def test_counters_box_clamped_to_the_viewport(oracle_lib):
+    """A square over pixel corners x in [-10, 10], y in [120, 140] of a 128^2
+    view: only columns 0..9 and rows 120..127 hold centres in the viewport,
+    so each half counts 10 x 8 = 80 tests, and 80 pixels are covered; a
+    square entirely left of the viewport has no survivor."""
+    pos, idx = quad(corner(-10, 120), corner(10, 120), corner(10, 140), corner(-10, 140))
+    st = stats_of(oracle_lib, pos, idx)
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (2, 160, 80)
+    pos, idx = quad(corner(-30, 50), corner(-10, 50), corner(-10, 60), corner(-30, 60))
+    st = stats_of(oracle_lib, pos, idx)
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (0, 0, 0)
+
+
+def test_counters_count_fragments_hidden_by_the_depth_test(oracle_lib):
+    """Two squares over the same 10 x 10 pixels, the nearer one (w = 1) drawn
+    first and the farther one (w = 2) second: both pass coverage on all 100
+    pixels, so covered = 200 although the farther one wins none."""
+    near = quad(corner(10, 30, 1.0), corner(20, 30, 1.0), corner(20, 40, 1.0), corner(10, 40, 1.0))
+    far = quad(corner(10, 30, 2.0), corner(20, 30, 2.0), corner(20, 40, 2.0), corner(10, 40, 2.0))
+    pos, idx, _ = merge(near, far)
+    r = oracle_lib.render_view(pos, None, idx, 128, 128, IDENT_POSE)
+    st = r["stats"]
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (4, 400, 200)
+    assert set(np.unique(r["tri"][r["tri"] != NONE]).tolist()) == {0, 1}
+
+
+def test_counters_face_on_cube(oracle_lib):
+    """The face-on unit cube (see test_cube_face_on): the front face's two
+    triangles have corners on the pixel corners (48, 48)..(80, 80), so each
+    box holds 32 x 32 centres and together they cover the 1024 pixels once.
+    Its back face (w = 3, half-width 0.5 m) spans x and y in
+    [64 - 32/3, 64 + 32/3] = [53.33, 74.67] px: centres 53..74, 22 x 22,
+    so 2 x 484 tests and 484 covered.  Side faces seen edge-on project to zero
+    area and are dropped, except the four visible through perspective
+    (left, right, top, bottom faces between w = 2 and 3), whose counts are
+    the oracle's business; the front face's share is exact."""
+    pos, idx = cube_scene()
+    st = stats_of(oracle_lib, pos, idx[:2])
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (2, 2048, 1024)
+    st = stats_of(oracle_lib, pos, idx[2:4])
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (2, 2 * 484, 484)
+
+
+def test_counters_degenerate_and_empty(oracle_lib):
+    """Degenerate triangles and geometry behind the camera count nothing."""
+    pos = np.array([[-1, 0, -2], [0, 0, -2], [1, 0, -2], [0.5, 0.5, -2]], np.float32)
+    idx = np.array([[0, 1, 2], [3, 3, 1], [0, 0, 0]], np.uint32)
+    st = stats_of(oracle_lib, pos, idx, 64)
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (0, 0, 0)
+    pos, idx = quad(corner(10, 30, -1.0), corner(20, 30, -1.0), corner(20, 40, -1.0), corner(10, 40, -1.0))
+    st = stats_of(oracle_lib, pos, idx)
+    assert (st["survivors"], st["bbox_tests"], st["covered"]) == (0, 0, 0)
