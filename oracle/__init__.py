@@ -10,10 +10,10 @@ caster used to pin the oracle on tiny scenes.
 """
 from .binding import (build, focal, pose_check, render_view, coverage_count,
                       project_point, render_views, semantic_image, philox4x64_10,
-                      depth_noise_normal, depth_noise, actuate, agent_pose, OR_OK, OR_ERR_INVALID_ARG,
+                      depth_noise_normal, depth_noise, actuate, agent_pose, nav_slice, nav_free, OR_OK, OR_ERR_INVALID_ARG,
                       OR_ERR_RANGE, NONE)
 
 __all__ = ["build", "focal", "pose_check", "render_view", "coverage_count",
            "project_point", "render_views", "semantic_image", "philox4x64_10",
-           "depth_noise_normal", "depth_noise", "actuate", "agent_pose", "OR_OK",
+           "depth_noise_normal", "depth_noise", "actuate", "agent_pose", "nav_slice", "nav_free", "OR_OK",
            "OR_ERR_INVALID_ARG", "OR_ERR_RANGE", "NONE"]

@@ -91,6 +91,11 @@ def _load():
             lib.or_actuate.restype = C.c_int
             lib.or_actuate.argtypes = [f32p, C.c_uint32, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_uint32, C.POINTER(Agent), u32p]
+            lib.or_nav_slice.restype = C.c_int64
+            lib.or_nav_slice.argtypes = [f32p, C.c_uint32, u32p, C.c_uint32, f64p, C.c_uint32, f32p,
+                                         C.c_uint64]
+            lib.or_nav_free.restype = C.c_int
+            lib.or_nav_free.argtypes = [f32p, C.c_uint32, C.c_double, C.c_double, C.c_double]
             lib.or_agent_pose.restype = None
             lib.or_agent_pose.argtypes = [C.POINTER(Agent), C.c_float, f32p]
             lib.or_depth_noise.restype = C.c_int
@@ -285,6 +290,35 @@ def actuate(segments, agents, actions, radius, step, turn_cos, turn_sin):
         out[k] = (a.x, a.z, a.fx, a.fz)
         hit[k] = bool(flag.value)
     return out, hit
+
+
+def nav_slice(positions, indices, heights):
+    """float32 [n, 4] obstacle segments: the mesh's cross-sections at the
+    given heights, in (triangle, height) order."""
+    pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
+    idx = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
+    hs = np.ascontiguousarray(heights, np.float64).reshape(-1)
+    lib = _load()
+    n = lib.or_nav_slice(_ptr(pos, C.c_float), pos.shape[0], _ptr(idx, C.c_uint32), idx.shape[0],
+                         _ptr(hs, C.c_double), hs.shape[0], None, 0)
+    if n < 0:
+        raise OracleError(OR_ERR_INVALID_ARG)
+    out = np.zeros((max(n, 1), 4), np.float32)
+    m = lib.or_nav_slice(_ptr(pos, C.c_float), pos.shape[0], _ptr(idx, C.c_uint32), idx.shape[0],
+                         _ptr(hs, C.c_double), hs.shape[0], _ptr(out, C.c_float), n)
+    assert m == n
+    return out[:n]
+
+
+def nav_free(segments, points, radius):
+    """bool [N]: is a disc of ``radius`` at each (x, z) of points [N, 2] free
+    of every segment?"""
+    seg = np.ascontiguousarray(segments, np.float32).reshape(-1, 4)
+    pts = np.asarray(points, np.float64).reshape(-1, 2)
+    lib = _load()
+    sp = _ptr(seg, C.c_float)
+    return np.array([bool(lib.or_nav_free(sp, seg.shape[0], float(x), float(z), float(radius)))
+                     for x, z in pts], bool)
 
 
 def agent_pose(agents, height):

@@ -780,3 +780,88 @@ void or_agent_pose(const or_agent *ag, float height, float pose[12])
         pose[3 + 3 * r + 2] = (float)back[r];
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Obstacles from the scene's own geometry and free space (Sec. 4 "Agent
+ * embodiment and action space": the agent is a 0.2 m-diameter, 1.5 m-tall
+ * cylinder; "Collision dynamics": it slides along the scene's walls and
+ * obstacles).  The paper describes no navigability representation; the
+ * written definition:
+ *
+ *   - the obstacles of a mesh are its horizontal cross-sections at K given
+ *     heights across the agent's body (above the floor, up to its height):
+ *     for each triangle in index order and each height h in the given order,
+ *     classify the vertices as above (y >= h) or below; when the classes
+ *     differ, exactly two edges (walked v0->v1, v1->v2, v2->v0) change class,
+ *     each is cut at y = h by interpolating from its lower end towards its
+ *     upper end, t = (h - lo.y) / (hi.y - lo.y), x = lo.x + t (hi.x - lo.x)
+ *     (the same for z), and the segment from the first cut to the second is
+ *     one obstacle (x0, z0, x1, z1), computed in fp64 and rounded once to
+ *     fp32 per coordinate;
+ *   - a disc of radius r at (x, z) is free when every obstacle segment is at
+ *     least r away: with e = b - a, L2 = |e|^2, s = ((p - a).e) / L2 clamped
+ *     to [0, 1] (s = 0 when L2 = 0), q = a + s e - p, the disc is blocked by
+ *     the segment when |q|^2 < r^2 (fp64, in that order).
+ * ---------------------------------------------------------------------- */
+
+/* Cross-section obstacles of a mesh.  seg_out [cap][4] (may be NULL when cap
+ * is 0); returns the number of segments (written up to cap), or -1 for an
+ * index out of range. */
+int64_t or_nav_slice(const float *pos, uint32_t V, const uint32_t *idx, uint32_t T, const double *heights,
+                     uint32_t K, float *seg_out, uint64_t cap)
+{
+    uint64_t n = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+        double P[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t vi = idx[3 * (size_t)t + k];
+            if (vi >= V) return -1;
+            for (int a = 0; a < 3; ++a) P[k][a] = (double)pos[3 * (size_t)vi + a];
+        }
+        for (uint32_t h = 0; h < K; ++h) {
+            const double y = heights[h];
+            int up[3];
+            for (int k = 0; k < 3; ++k) up[k] = P[k][1] >= y;
+            if (up[0] == up[1] && up[1] == up[2]) continue;
+            double cut[2][2];
+            int nc = 0;
+            for (int k = 0; k < 3; ++k) {
+                const double *a = P[k], *b = P[(k + 1) % 3];
+                if (up[k] == up[(k + 1) % 3]) continue;
+                const double *lo = up[k] ? b : a, *hi = up[k] ? a : b;
+                const double s = (y - lo[1]) / (hi[1] - lo[1]);
+                cut[nc][0] = lo[0] + s * (hi[0] - lo[0]);
+                cut[nc][1] = lo[2] + s * (hi[2] - lo[2]);
+                ++nc;
+            }
+            if (n < cap) {
+                float *o = seg_out + 4 * n;
+                o[0] = (float)cut[0][0];
+                o[1] = (float)cut[0][1];
+                o[2] = (float)cut[1][0];
+                o[3] = (float)cut[1][1];
+            }
+            ++n;
+        }
+    }
+    return (int64_t)n;
+}
+
+/* 1 when a disc of radius r at (px, pz) is free of every segment. */
+int or_nav_free(const float *seg, uint32_t nseg, double px, double pz, double r)
+{
+    for (uint32_t k = 0; k < nseg; ++k) {
+        const double ax = seg[4 * (size_t)k], az = seg[4 * (size_t)k + 1];
+        const double ex = (double)seg[4 * (size_t)k + 2] - ax, ez = (double)seg[4 * (size_t)k + 3] - az;
+        const double L2 = ex * ex + ez * ez;
+        double s = 0.0;
+        if (L2 > 0.0) {
+            s = ((px - ax) * ex + (pz - az) * ez) / L2;
+            if (s < 0.0) s = 0.0;
+            if (s > 1.0) s = 1.0;
+        }
+        const double qx = ax + s * ex - px, qz = az + s * ez - pz;
+        if (qx * qx + qz * qz < r * r) return 0;
+    }
+    return 1;
+}
