@@ -1,14 +1,18 @@
 """Full-size workloads, in the launch configurations the benchmark times.
 
 The 64-environment batch (4 jittered apartments of 100k-1M triangles,
-256x256 RGB+D) is one hab_render_batch call per step with default options;
-the 256-environment mixed batch (16 apartments of 50k-1.5M triangles, 128/
-256/512 px, depth / RGB / RGB+D sensors) runs through the captured stepper.
-One view per environment every 50 steps of the 500-step walks is compared
-with the oracle (ids bit-exact, depth within 1e-5 relative, colour within
-1/255, work counters exact); every view is checked for what holds at any
-size; the stepper's replay must equal an eager batch bit for bit; the
-autotuner's choice must not change a bit.
+256x256 RGB+D) is one hab_render_batch call per step; it runs at each tile
+size the autotuner may pick (8, 16 and 32 pixels), with the autotuner's own
+choice, and through the lossless overflow path (a tile capacity of 64 list
+entries; a bin capacity of a quarter of the triangle count).  The
+256-environment mixed batch (16 apartments of 50k-1.5M triangles, 128/256/
+512 px, depth / RGB / RGB+D sensors) runs through the captured stepper at
+the default tile and at 8 and 32 pixels.  One view per environment every
+50 steps of the 500-step walks is compared with the oracle (ids
+bit-exact, depth within 1e-5 relative, colour within 1/255, work counters
+exact); every view is checked for what holds at any size; the stepper's
+replay must equal an eager batch bit for bit; the autotuner's choice must
+not change a bit.
 """
 import numpy as np
 import pytest
@@ -28,36 +32,71 @@ def ctx():
     c.close()
 
 
-def test_batch64_sampled_steps(ctx):
-    import torch
-    note("batch64_4scenes_256: hab_render_batch, every 50th step vs oracle")
+@pytest.fixture(scope="module")
+def batch64(ctx):
     w = configs.batch64_4scenes_256(steps=500)
     hs = [ctx.upload_scene(s) for s in w.scenes]
+    yield w, hs
+    for h in hs:
+        ctx.release(h)
+
+
+# (label, render options): the default tile, each autotuner candidate, and
+# the overflow path at the 8-pixel tile the benchmark's autotune picks (its
+# tile lists hold about 100 entries on average, so a cap of 64 sends many
+# tiles through the overflow scan; a quarter of T bin entries per view runs
+# out of list space for the last tiles of most views)
+BATCH64_OPTS = [
+    ("default", {}),
+    ("tile8", {"tile_size": 8}),
+    ("tile32", {"tile_size": 32}),
+    ("tile8_cap64", {"tile_size": 8, "tile_cap": 64}),
+    ("tile8_bins0.25", {"tile_size": 8, "bin_factor": 0.25}),
+    ("autotuned", None),
+]
+
+
+@pytest.mark.parametrize("label,opts", BATCH64_OPTS, ids=[o[0] for o in BATCH64_OPTS])
+def test_batch64_sampled_steps(ctx, batch64, label, opts):
+    import torch
+    w, hs = batch64
+    note(f"batch64_4scenes_256 [{label}]: hab_render_batch, every 50th step vs oracle")
     sn = ctx.sensor(256, 256)
+    if opts is None:
+        # the benchmark's own tuning call: step-0 poses, RGB + depth only
+        o0 = ctx.alloc(sn, w.num_envs)
+        items0 = [(hs[w.env_scene[e]], sn, w.poses[0, e], o0["rgb"][e], o0["depth"][e], None)
+                  for e in range(w.num_envs)]
+        ts, bf = ctx.autotune(items0)
+        assert ts in (8, 16, 32) and bf in (1.0, 2.0, 4.0), (ts, bf)
+        note(f"batch64 autotuned: tile {ts}, bin factor {bf}")
+        del o0, items0
+        opts = {}
     out = ctx.alloc(sn, w.num_envs, tri=True)
     views = 0
     for step in SAMPLE_STEPS:
-        note(f"batch64 step {step}")
+        note(f"batch64 [{label}] step {step}")
         items = [(hs[w.env_scene[e]], sn, w.poses[step, e], out["rgb"][e], out["depth"][e],
                   out["tri"][e]) for e in range(w.num_envs)]
-        stats = ctx.render_batch(items, stats=True)
+        stats = ctx.render_batch(items, stats=True, **opts)
         torch.cuda.synchronize()
         g = to_np(out)
         jobs = []
         for e in range(w.num_envs):
             sc = w.scenes[w.env_scene[e]]
             ge = {k: v[e] for k, v in g.items()}
-            check_any_size(ge, sc.num_triangles, f"step {step} env {e}")
-            jobs.append((sc, w.env_sensor[e], w.poses[step, e], ge, stats[e], f"step {step} env {e}"))
+            check_any_size(ge, sc.num_triangles, f"[{label}] step {step} env {e}")
+            jobs.append((sc, w.env_sensor[e], w.poses[step, e], ge, stats[e],
+                         f"[{label}] step {step} env {e}"))
         views += oracle_compare_many(jobs)
-    note(f"batch64: {views} views match the oracle")
-    for h in hs:
-        ctx.release(h)
+    note(f"batch64 [{label}]: {views} views match the oracle")
+    assert ctx.get_error() == 0
 
 
-def test_mixed256_stepper_sampled_steps(ctx):
+@pytest.mark.parametrize("tile_size", [0, 8, 32], ids=["default", "tile8", "tile32"])
+def test_mixed256_stepper_sampled_steps(ctx, tile_size):
     import torch
-    note("batch256_16scenes_mixed: stepper, every 50th step vs oracle")
+    note(f"batch256_16scenes_mixed [tile {tile_size}]: stepper, every 50th step vs oracle")
     w = configs.batch256_16scenes_mixed(steps=500)
     hs = [ctx.upload_scene(s) for s in w.scenes]
     sensors = {}
@@ -74,7 +113,7 @@ def test_mixed256_stepper_sampled_steps(ctx):
         return outs, items
 
     outs_g, items_g = make_items(0)
-    st = ctx.stepper(items_g)
+    st = ctx.stepper(items_g, tile_size=tile_size)
     views = 0
     for n, step in enumerate(SAMPLE_STEPS):
         note(f"mixed256 step {step}")
@@ -82,7 +121,7 @@ def test_mixed256_stepper_sampled_steps(ctx):
         torch.cuda.synchronize()
         if n == 0:
             outs_e, items_e = make_items(step)
-            ctx.render_batch(items_e)
+            ctx.render_batch(items_e, tile_size=tile_size)
             torch.cuda.synchronize()
             for e in range(w.num_envs):
                 for k in outs_g[e]:
