@@ -129,16 +129,23 @@ def other_workloads(ctx, a):
     return out
 
 
-def actuation_leg(ctx, w, a):
+NAV_HEIGHTS = (0.1, 1.5)   # cross-section heights of the agent's body (just above the floor; its top)
+
+
+def actuation_leg(ctx, w, a, hs):
     """The agent step before rendering: batched actuation with
     collide-and-slide for 16,384 agents per scene of the bench workload
     (65,536 agents), uniformly random actions (forward twice as likely as
-    each turn), timed over the bench's step count."""
+    each turn), timed over the bench's step count; the obstacles are the
+    rendered meshes' own cross-sections (hab_nav_from_scene).  Then batched
+    free-space queries: 1M random floor points per scene."""
     import torch
-    from scenegen import agents_from_states, nav_segments
+    from scenegen import agents_from_states
     from scenegen.walks import random_free_states
     per = 16384
-    navs = [ctx.nav_upload(nav_segments(s)) for s in w.scenes]
+    t0 = time.perf_counter()
+    navs = [ctx.nav_from_scene(h, NAV_HEIGHTS) for h in hs]
+    t_nav = time.perf_counter() - t0
     states, owner = [], []
     for i, s in enumerate(w.scenes):
         x, z, yaw = random_free_states(s, per, seed=500 + i)
@@ -160,13 +167,37 @@ def actuation_leg(ctx, w, a):
         ctx.actuate(nav_of, ag, acts[a.warmup + s], hit, poses)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # free-space queries
+    nq = 1 << 20
+    pts, outs = [], []
+    for s in w.scenes:
+        lo, hi = s.positions.min(0), s.positions.max(0)
+        p = np.stack([rng.uniform(lo[0], hi[0], nq), rng.uniform(lo[2], hi[2], nq)], 1)
+        pts.append(torch.from_numpy(p).cuda())
+        outs.append(torch.empty(nq, dtype=torch.uint8, device="cuda"))
+    for i, nv in enumerate(navs):
+        ctx.nav_free(nv, pts[i], 0.1, outs[i])
+    torch.cuda.synchronize()
+    qsteps = max(1, min(steps, 20))
+    t0 = time.perf_counter()
+    for _ in range(qsteps):
+        for i, nv in enumerate(navs):
+            ctx.nav_free(nv, pts[i], 0.1, outs[i])
+    torch.cuda.synchronize()
+    el_q = time.perf_counter() - t0
+    free_frac = float(np.mean([o.float().mean().item() for o in outs]))
     for nv in navs:
         ctx.nav_release(nv)
     out = {"agents": n, "scenes": len(w.scenes), "segments": [int(nv.num_segments) for nv in navs],
+           "obstacles": f"mesh cross-sections at {list(NAV_HEIGHTS)} m (hab_nav_from_scene)",
+           "nav_from_scene_s": round(t_nav, 4),
            "steps": steps, "agent_steps_per_s": round(n * steps / el), "ms_per_step": round(1e3 * el / steps, 4),
-           "path": "hab_actuate (fp64 collide-and-slide over a uniform 0.5 m grid of obstacle segments)"}
+           "path": "hab_actuate (fp64 collide-and-slide over a uniform 0.5 m grid of obstacle segments)",
+           "free_space_queries_per_s": round(len(navs) * nq * qsteps / el_q),
+           "free_space_query": f"hab_nav_free, {nq} random points per scene, radius 0.1 m, "
+                               f"{free_frac:.2f} free"}
     log(f"actuation: {out['agent_steps_per_s']:.3g} agent steps/s ({out['ms_per_step']} ms per "
-        f"{n}-agent step)")
+        f"{n}-agent step); free space: {out['free_space_queries_per_s']:.3g} queries/s")
     return out
 
 
@@ -334,9 +365,9 @@ def main():
     # ---------------------------------------------------- env loop
     # the whole environment step on the device: actuation of the 64 agents
     # (random actions, collide-and-slide) feeding the captured render step
-    from scenegen import agents_from_states, nav_segments
+    from scenegen import agents_from_states
     from scenegen.walks import random_free_states
-    navs_h = [ctx.nav_upload(nav_segments(s)) for s in w.scenes]
+    navs_h = [ctx.nav_from_scene(h, NAV_HEIGHTS) for h in hs]
     ag_np = np.concatenate([agents_from_states(*random_free_states(w.scenes[w.env_scene[e]], 1, seed=900 + e))
                             for e in range(E)])
     ag = torch.from_numpy(ag_np).cuda()
@@ -487,7 +518,7 @@ def main():
 
     # ---------------------------------------------------- the other workloads
     others = {} if a.no_other_workloads else other_workloads(ctx, a)
-    actuation = actuation_leg(ctx, w, a)
+    actuation = actuation_leg(ctx, w, a, hs)
 
     # ---------------------------------------------------- CPU oracle baseline
     cpu = None

@@ -245,6 +245,7 @@ hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sen
 hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t num_views,
                             const hab_render_opts *opts, hipStream_t stream);
 
+
 /* ---------------------------------------------------------- actuation */
 /* The agent step before rendering (Sec. 4 "Agent embodiment and action
  * space", "Collision dynamics"): an agent is a vertical cylinder (a disc of
@@ -252,8 +253,9 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t nu
  * forward in a continuous state space; a forward move that meets an
  * obstacle makes partial or no progress and may slide along it.
  *
- * Obstacles are line segments on the floor plane (x0, z0, x1, z1), the
- * boundary of the free floor, uploaded once per scene. */
+ * Obstacles are line segments on the floor plane (x0, z0, x1, z1), made
+ * once per scene: from the scene's own mesh (hab_nav_from_scene) or given
+ * by the caller (hab_nav_upload). */
 typedef struct hab_nav hab_nav;
 
 /* segments: host [num_segments][4] float, metres (finite; a zero-length
@@ -261,7 +263,44 @@ typedef struct hab_nav hab_nav;
  * copied. */
 hab_status hab_nav_upload(hab_context *ctx, const float *segments, uint32_t num_segments,
                           hab_nav **out);
+
+/* Obstacles from the scene's own geometry, so that agents collide with what
+ * is rendered (Sec. 4 "Collision dynamics": the agent slides along the
+ * scene's walls and obstacles; the paper gives no navigability
+ * representation).  The obstacles are the mesh's horizontal cross-sections
+ * at num_heights (1..HAB_NAV_MAX_HEIGHTS) heights across the agent's body
+ * (heights: host array, metres, finite; e.g. 0.1 and 1.5 for the paper's
+ * 1.5 m agent: just above the floor, where every piece of furniture
+ * stands, and its top): for each triangle in index order and each height h
+ * in the given order, a vertex is above when its y >= h; when the three
+ * vertices are not all on one side, the two edges (walked v0->v1, v1->v2,
+ * v2->v0) that change side are cut at y = h by interpolating from the
+ * edge's lower end to its upper end, s = (h - lo.y) / (hi.y - lo.y),
+ * x = lo.x + s (hi.x - lo.x) (z alike), and the segment from the first cut
+ * to the second is one obstacle, computed in fp64 and rounded once to fp32
+ * per coordinate.  The cross-sections are computed on the device from the
+ * scene's resident geometry (one kernel pass counting, one writing); the
+ * lookup grid is built as by hab_nav_upload.  Synchronous with respect to
+ * the host (stream is used for the kernels and copies). */
+#define HAB_NAV_MAX_HEIGHTS 16
+hab_status hab_nav_from_scene(hab_context *ctx, const hab_scene *scene, const double *heights,
+                              uint32_t num_heights, hipStream_t stream, hab_nav **out);
+/* Copy an obstacle set's segments (in their order) to host [capacity][4]
+ * floats; *num_segments gets the set's count (the first capacity are
+ * written).  Synchronous. */
+hab_status hab_nav_segments(hab_context *ctx, const hab_nav *nav, float *out, uint32_t capacity,
+                            uint32_t *num_segments);
 hab_status hab_nav_release(hab_context *ctx, hab_nav *nav);
+
+/* Free-space query (navigability, Sec. 4 "Agent embodiment and action
+ * space"): out_free[i] = 1 when a disc of radius at points[i] = (x, z) is
+ * clear of every segment of nav (each at least radius away: with
+ * e = b - a, L2 = |e|^2, s = ((p - a).e) / L2 clamped to [0, 1] (0 when
+ * L2 = 0), q = a + s e - p, blocked when |q|^2 < radius^2; fp64), else 0.
+ * points: device [n][2] double; out_free: device [n] uint8; radius > 0 and
+ * finite.  Asynchronous on the stream. */
+hab_status hab_nav_free(hab_context *ctx, const hab_nav *nav, const double *points, uint32_t n,
+                        double radius, uint8_t *out_free, hipStream_t stream);
 
 /* Agent state: position on the floor plane and the unit forward vector
  * (yaw 0 looks along -z: (fx, fz) = (-sin yaw, -cos yaw)). */

@@ -34,7 +34,8 @@ EXPORTED = [
     "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
     "hab_profile_enable", "hab_profile_phases", "hab_profile_read",
-    "hab_nav_upload", "hab_nav_release", "hab_actuate", "hab_selfcheck_reciprocal",
+    "hab_nav_upload", "hab_nav_from_scene", "hab_nav_segments", "hab_nav_free", "hab_nav_release",
+    "hab_actuate", "hab_selfcheck_reciprocal",
 ]
 ACT_STOP, ACT_FORWARD, ACT_LEFT, ACT_RIGHT = 0, 1, 2, 3
 PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "raster16",
@@ -162,6 +163,9 @@ def load():
             "hab_profile_phases": [vp, C.c_uint32],
             "hab_profile_read": [vp, C.POINTER(PhaseTimes)],
             "hab_nav_upload": [vp, vp, u32, C.POINTER(vp)],
+            "hab_nav_from_scene": [vp, vp, vp, u32, vp, C.POINTER(vp)],
+            "hab_nav_segments": [vp, vp, vp, u32, C.POINTER(u32)],
+            "hab_nav_free": [vp, vp, vp, u32, C.c_double, vp, vp],
             "hab_nav_release": [vp, vp],
             "hab_actuate": [vp, C.POINTER(vp), u32, vp, vp, vp, vp, f32, C.POINTER(Actuation), vp],
             "hab_selfcheck_reciprocal": [vp, u32, u32, vp, C.POINTER(C.c_uint64)],

@@ -259,6 +259,173 @@ __global__ __launch_bounds__(kActBlock) void k_actuate(const NavDesc *__restrict
     }
 }
 
+// ------------------------------------------------------------ obstacles from the mesh
+// Horizontal cross-sections of the scene's triangles at K heights (the
+// agent's body between just above the floor and its top; the definition is
+// stated with hab_nav_from_scene in hab.h): per triangle, the mask of the
+// heights whose plane separates its vertices; a block scan of the counts
+// gives each triangle's first output slot, so the segments come out in
+// (triangle, height) order.
+constexpr int kSliceBlock = 256;
+
+struct SliceParams {
+    double h[HAB_NAV_MAX_HEIGHTS];
+    uint32_t K;
+};
+
+__device__ __forceinline__ void load_tri_pos(const float *__restrict__ tpos, uint32_t t, double P[3][3])
+{
+    const float *p = tpos + 9ull * t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P[k][a] = (double)p[3 * k + a];
+}
+
+// Heights (bit h) whose plane has vertices of the triangle on both sides
+// (a vertex at exactly the height counts as above).
+__device__ __forceinline__ uint32_t slice_mask(const double P[3][3], const SliceParams &S)
+{
+    uint32_t m = 0;
+    for (uint32_t h = 0; h < S.K; ++h) {
+        const double y = S.h[h];
+        const bool u0 = P[0][1] >= y, u1 = P[1][1] >= y, u2 = P[2][1] >= y;
+        if (!(u0 == u1 && u1 == u2)) m |= 1u << h;
+    }
+    return m;
+}
+
+// Exclusive scan of x over the block (wave64 shuffles + one LDS word per
+// wave); *total gets the block's sum.
+__device__ __forceinline__ uint32_t slice_block_scan(uint32_t x, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kSliceBlock / 64];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    uint32_t s = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(s, off);
+        if (lane >= (uint32_t)off) s += y;
+    }
+    if (lane == 63) wsum[wave] = s;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSliceBlock / 64; ++w) {
+        const uint32_t v = wsum[w];
+        pre += (w < (int)wave) ? v : 0u;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + s - x;
+}
+
+__global__ __launch_bounds__(kSliceBlock) void k_slice_count(const float *__restrict__ tpos, uint32_t T,
+                                                             SliceParams S, uint32_t *__restrict__ block_total)
+{
+    const uint32_t t = blockIdx.x * kSliceBlock + threadIdx.x;
+    uint32_t c = 0;
+    if (t < T) {
+        double P[3][3];
+        load_tri_pos(tpos, t, P);
+        c = (uint32_t)__popc(slice_mask(P, S));
+    }
+    uint32_t tot;
+    (void)slice_block_scan(c, &tot);
+    if (threadIdx.x == 0) block_total[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kSliceBlock) void k_slice_write(const float *__restrict__ tpos, uint32_t T,
+                                                             SliceParams S,
+                                                             const uint32_t *__restrict__ block_base,
+                                                             float4 *__restrict__ seg)
+{
+    const uint32_t t = blockIdx.x * kSliceBlock + threadIdx.x;
+    double P[3][3] = {};
+    uint32_t m = 0;
+    if (t < T) {
+        load_tri_pos(tpos, t, P);
+        m = slice_mask(P, S);
+    }
+    uint32_t tot;
+    uint32_t o = block_base[blockIdx.x] + slice_block_scan((uint32_t)__popc(m), &tot);
+    for (uint32_t h = 0; h < S.K; ++h) {
+        if (!((m >> h) & 1u)) continue;
+        const double y = S.h[h];
+        bool up[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) up[k] = P[k][1] >= y;
+        // the two edges (walked v0->v1, v1->v2, v2->v0) that change side,
+        // each cut by interpolation from its lower end to its upper end
+        double cx[2] = {0.0, 0.0}, cz[2] = {0.0, 0.0};
+        int nc = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = (k + 1) % 3;
+            if (up[k] == up[k1]) continue;
+            const double *lo = up[k] ? P[k1] : P[k];
+            const double *hi = up[k] ? P[k] : P[k1];
+            const double s = (y - lo[1]) / (hi[1] - lo[1]);
+            cx[nc] = lo[0] + s * (hi[0] - lo[0]);
+            cz[nc] = lo[2] + s * (hi[2] - lo[2]);
+            ++nc;
+        }
+        seg[o++] = make_float4((float)cx[0], (float)cz[0], (float)cx[1], (float)cz[1]);
+    }
+}
+
+// Free-space query: is a disc of radius r at (x, z) clear of every segment
+// (each at least r away)?  One lane per point, over the grid cells under
+// the disc's box grown by a 0.1 mm margin (a segment that comes within r
+// has its box meet the disc's, so it is listed in one of those cells);
+// the per-segment test is the fp64 point-segment distance with the
+// parameter clamped to the segment.
+__global__ __launch_bounds__(kActBlock) void k_nav_free(NavDesc D, const double2 *__restrict__ pts, uint32_t n,
+                                                        double r, uint8_t *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * kActBlock + threadIdx.x;
+    if (i >= n) return;
+    const double2 p = pts[i];
+    const double px = p.x, pz = p.y, r2 = r * r;
+    bool blocked = false;
+    const float grow = (float)r + 1e-4f;
+    const float qx0 = (float)px - grow, qx1 = (float)px + grow;
+    const float qz0 = (float)pz - grow, qz1 = (float)pz + grow;
+    const bool inside = D.gx && qx1 >= D.ox && qz1 >= D.oz && qx0 <= D.ox + D.h * (float)D.gx &&
+                        qz0 <= D.oz + D.h * (float)D.gz;
+    if (inside) {
+        const int cx0 = cell_of(qx0, D.ox, D.inv_h, D.gx), cx1 = cell_of(qx1, D.ox, D.inv_h, D.gx);
+        const int cz0 = cell_of(qz0, D.oz, D.inv_h, D.gz), cz1 = cell_of(qz1, D.oz, D.inv_h, D.gz);
+        for (int cz = cz0; cz <= cz1 && !blocked; ++cz)
+            for (int cx = cx0; cx <= cx1 && !blocked; ++cx) {
+                const uint32_t c = (uint32_t)cz * D.gx + (uint32_t)cx;
+                const uint32_t i1 = D.cell_start[c + 1];
+                for (uint32_t k = D.cell_start[c]; k < i1; ++k) {
+                    const float4 sg = D.seg[D.items[k]];
+                    if (fminf(sg.x, sg.z) > qx1 || fmaxf(sg.x, sg.z) < qx0 || fminf(sg.y, sg.w) > qz1 ||
+                        fmaxf(sg.y, sg.w) < qz0)
+                        continue;
+                    const double ax = sg.x, az = sg.y;
+                    const double ex = (double)sg.z - ax, ez = (double)sg.w - az;
+                    const double L2 = ex * ex + ez * ez;
+                    double s = 0.0;
+                    if (L2 > 0.0) {
+                        s = ((px - ax) * ex + (pz - az) * ez) / L2;
+                        s = s < 0.0 ? 0.0 : s;
+                        s = s > 1.0 ? 1.0 : s;
+                    }
+                    const double qx = ax + s * ex - px, qz = az + s * ez - pz;
+                    if (qx * qx + qz * qz < r2) {
+                        blocked = true;
+                        break;
+                    }
+                }
+            }
+    }
+    out[i] = blocked ? 0 : 1;
+}
+
 }  // namespace
 
 void release_navs(hab_context *ctx)
@@ -275,15 +442,13 @@ void release_navs(hab_context *ctx)
 
 using namespace habmi;
 
-extern "C" {
+namespace habmi {
 
-hab_status hab_nav_upload(hab_context *ctx, const float *segments, uint32_t num_segments, hab_nav **out)
+// An obstacle set from host segments: the grid built here, segments, cell
+// starts and cell lists copied to one device allocation.
+static hab_status nav_build(hab_context *ctx, const float *segments, uint32_t num_segments, hab_nav **out)
 {
-    if (!ctx || !out || (num_segments && !segments)) return HAB_ERR_INVALID_ARG;
-    *out = nullptr;
-    return guarded([&]() -> hab_status {
-        for (uint64_t k = 0; k < 4ull * num_segments; ++k)
-            if (!std::isfinite(segments[k])) return HAB_ERR_INVALID_ARG;
+    {
         // the grid: cells of kNavCell (larger when the extent needs more
         // than kNavMaxDim cells per axis) over the segments' bounding box
         NavDesc d{};
@@ -354,6 +519,21 @@ hab_status hab_nav_upload(hab_context *ctx, const float *segments, uint32_t num_
         ctx->navs.push_back(n);
         *out = n;
         return HAB_OK;
+    }
+}
+
+}  // namespace habmi
+
+extern "C" {
+
+hab_status hab_nav_upload(hab_context *ctx, const float *segments, uint32_t num_segments, hab_nav **out)
+{
+    if (!ctx || !out || (num_segments && !segments)) return HAB_ERR_INVALID_ARG;
+    *out = nullptr;
+    return guarded([&]() -> hab_status {
+        for (uint64_t k = 0; k < 4ull * num_segments; ++k)
+            if (!std::isfinite(segments[k])) return HAB_ERR_INVALID_ARG;
+        return nav_build(ctx, segments, num_segments, out);
     });
 }
 
@@ -446,6 +626,104 @@ hab_status hab_actuate(hab_context *ctx, const hab_nav *const *navs, uint32_t n,
         HAB_HIP(hipEventRecord(ws.done, stream));
         ws.has_done = true;
         ws.last_stream = stream;
+        return HAB_OK;
+    });
+}
+
+
+hab_status hab_nav_from_scene(hab_context *ctx, const hab_scene *scene, const double *heights, uint32_t num_heights,
+                              hipStream_t stream, hab_nav **out)
+{
+    if (!ctx || !scene || !out || !heights || num_heights == 0 || num_heights > HAB_NAV_MAX_HEIGHTS)
+        return HAB_ERR_INVALID_ARG;
+    *out = nullptr;
+    for (uint32_t h = 0; h < num_heights; ++h)
+        if (!std::isfinite(heights[h])) return HAB_ERR_INVALID_ARG;
+    if (std::find(ctx->scenes.begin(), ctx->scenes.end(), static_cast<const Scene *>(scene)) == ctx->scenes.end())
+        return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        const uint32_t T = scene->T;
+        std::vector<float> segs;
+        if (T) {
+            SliceParams S{};
+            for (uint32_t h = 0; h < num_heights; ++h) S.h[h] = heights[h];
+            S.K = num_heights;
+            const uint32_t nb = (T + kSliceBlock - 1) / kSliceBlock;
+            uint32_t *dtot = nullptr;
+            if (hipMalloc(&dtot, 8ull * nb) != hipSuccess) {
+                (void)hipGetLastError();
+                return HAB_ERR_OUT_OF_MEMORY;
+            }
+            uint32_t *dbase = dtot + nb;
+            std::vector<uint32_t> tot(nb), base(nb);
+            float4 *dseg = nullptr;
+            auto fail = [&](hab_status st) {
+                (void)hipFree(dtot);
+                if (dseg) (void)hipFree(dseg);
+                return st;
+            };
+            hipLaunchKernelGGL(k_slice_count, dim3(nb), dim3(kSliceBlock), 0, stream, scene->tpos, T, S, dtot);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(tot.data(), dtot, 4ull * nb, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return fail(HAB_ERR_DEVICE);
+            uint64_t nseg = 0;
+            for (uint32_t b = 0; b < nb; ++b) {
+                base[b] = (uint32_t)nseg;
+                nseg += tot[b];
+            }
+            if (nseg >= (1ull << 31)) return fail(HAB_ERR_CAPACITY);
+            if (nseg) {
+                if (hipMalloc(&dseg, 16ull * nseg) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(HAB_ERR_OUT_OF_MEMORY);
+                }
+                segs.resize(4ull * nseg);
+                if (hipMemcpyAsync(dbase, base.data(), 4ull * nb, hipMemcpyHostToDevice, stream) != hipSuccess)
+                    return fail(HAB_ERR_DEVICE);
+                hipLaunchKernelGGL(k_slice_write, dim3(nb), dim3(kSliceBlock), 0, stream, scene->tpos, T, S, dbase,
+                                   dseg);
+                if (hipGetLastError() != hipSuccess ||
+                    hipMemcpyAsync(segs.data(), dseg, 16ull * nseg, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                    hipStreamSynchronize(stream) != hipSuccess)
+                    return fail(HAB_ERR_DEVICE);
+            }
+            (void)fail(HAB_OK);
+        }
+        return nav_build(ctx, segs.data(), (uint32_t)(segs.size() / 4), out);
+    });
+}
+
+hab_status hab_nav_segments(hab_context *ctx, const hab_nav *nav, float *out, uint32_t capacity, uint32_t *num_segments)
+{
+    if (!ctx || !nav || !num_segments || (capacity && !out)) return HAB_ERR_INVALID_ARG;
+    return guarded([&]() -> hab_status {
+        if (std::find(ctx->navs.begin(), ctx->navs.end(), nav) == ctx->navs.end()) return HAB_ERR_INVALID_ARG;
+        *num_segments = nav->n;
+        const uint32_t m = std::min(capacity, nav->n);
+        if (!m) return HAB_OK;
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        HAB_HIP(hipMemcpy(out, nav->d.seg, 16ull * m, hipMemcpyDeviceToHost));
+        return HAB_OK;
+    });
+}
+
+hab_status hab_nav_free(hab_context *ctx, const hab_nav *nav, const double *points, uint32_t n, double radius,
+                        uint8_t *out_free, hipStream_t stream)
+{
+    if (!ctx || !nav || (n && (!points || !out_free))) return HAB_ERR_INVALID_ARG;
+    if (!(radius > 0.0) || !std::isfinite(radius)) return HAB_ERR_INVALID_ARG;
+    if (n == 0) return HAB_OK;
+    return guarded([&]() -> hab_status {
+        if (std::find(ctx->navs.begin(), ctx->navs.end(), nav) == ctx->navs.end()) return HAB_ERR_INVALID_ARG;
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return HAB_ERR_DEVICE;
+        hipLaunchKernelGGL(k_nav_free, dim3((n + kActBlock - 1) / kActBlock), dim3(kActBlock), 0, stream, nav->d,
+                           reinterpret_cast<const double2 *>(points), n, radius, out_free);
+        HAB_HIP(hipGetLastError());
         return HAB_OK;
     });
 }

@@ -309,6 +309,39 @@ class Context:
                                         seg.shape[0], C.byref(out)), "hab_nav_upload")
         return NavHandle(out.value, seg.shape[0])
 
+    def nav_from_scene(self, scene: SceneHandle, heights=(0.1, 1.5), stream=None) -> "NavHandle":
+        """Obstacles from the scene's own mesh: its cross-sections at the
+        given heights, computed on the device."""
+        hs = np.ascontiguousarray(heights, np.float64).reshape(-1)
+        out = C.c_void_p()
+        B.check(self.lib.hab_nav_from_scene(self.h, C.c_void_p(scene.ptr), hs.ctypes.data, hs.shape[0],
+                                            _stream_ptr(stream), C.byref(out)), "hab_nav_from_scene")
+        n = C.c_uint32()
+        B.check(self.lib.hab_nav_segments(self.h, out.value, None, 0, C.byref(n)), "hab_nav_segments")
+        return NavHandle(out.value, int(n.value))
+
+    def nav_segments(self, nav: "NavHandle") -> np.ndarray:
+        """The obstacle set's segments [n, 4] float32, in order."""
+        seg = np.zeros((max(nav.num_segments, 1), 4), np.float32)
+        n = C.c_uint32()
+        B.check(self.lib.hab_nav_segments(self.h, C.c_void_p(nav.ptr), seg.ctypes.data, nav.num_segments, C.byref(n)),
+                "hab_nav_segments")
+        return seg[:n.value]
+
+    def nav_free(self, nav: "NavHandle", points, radius=0.1, out=None, stream=None):
+        """uint8 [N] device tensor: 1 where a disc of ``radius`` at each (x, z)
+        of points (device float64 [N, 2]) is clear of the obstacles."""
+        torch = _torch()
+        assert points.dtype == torch.float64 and points.is_cuda and points.is_contiguous()
+        assert points.dim() == 2 and points.shape[1] == 2
+        n = points.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=points.device)
+        assert out.dtype == torch.uint8 and out.numel() >= n and out.is_contiguous()
+        B.check(self.lib.hab_nav_free(self.h, C.c_void_p(nav.ptr), _ptr(points), n, float(radius), _ptr(out),
+                                      _stream_ptr(stream)), "hab_nav_free")
+        return out
+
     def nav_release(self, nav: "NavHandle"):
         B.check(self.lib.hab_nav_release(self.h, C.c_void_p(nav.ptr)), "hab_nav_release")
 
