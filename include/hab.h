@@ -72,7 +72,7 @@ typedef enum {
     HAB_ERR_RANGE = 3,         /* pose/scene outside the fixed-point domain          */
     HAB_ERR_DEVICE = 4,        /* a HIP call failed                                  */
     HAB_ERR_NOT_READY = 5,     /* poll: the request has not completed yet            */
-    HAB_ERR_CAPACITY = 6       /* server: queue full / request larger than budget    */
+    HAB_ERR_CAPACITY = 6       /* queue full, request over budget, or beyond a limit */
 } hab_status;
 
 #define HAB_NO_HIT 0xFFFFFFFFu
@@ -244,7 +244,26 @@ hab_status hab_render_ex(hab_context *ctx, const hab_scene *scene, const hab_sen
  * of one scene read its geometry while it is in cache. */
 hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t num_views,
                             const hab_render_opts *opts, hipStream_t stream);
-
+/* hab_render for callers that cannot allocate memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and outputs as hab_render (default options; depth
+ * noise seed = pose index), but the launch's scratch memory is one static
+ * device array of 64 MiB per GPU, held from the library's load until the
+ * process ends, and the pinned staging and host planning buffers are
+ * reserved by hab_init.  The call allocates no device, pinned or host
+ * memory.
+ *
+ * Limits: num_poses <= 256 and the launch's scratch (about 50 MB for one
+ * 256x256 view of a 1M-triangle scene at the largest tuned capacity) must
+ * fit the array: beyond either, HAB_ERR_CAPACITY before anything is
+ * enqueued.  Every call on one GPU shares that GPU's array (whatever the
+ * context) and finds it holding the previous call's contents (each launch
+ * clears what must start at zero itself); calls that overlap on one GPU
+ * race, so order them (e.g. one stream, or events between streams).
+ * Outputs, poses and errors as hab_render. */
+hab_status hab_render_noalloc(hab_context *ctx, const hab_scene *scene, const hab_sensor *sensor,
+                              const hab_pose *poses, uint32_t num_poses, uint8_t *out_rgb,
+                              float *out_depth, hipStream_t stream);
 
 /* ---------------------------------------------------------- actuation */
 /* The agent step before rendering (Sec. 4 "Agent embodiment and action

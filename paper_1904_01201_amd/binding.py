@@ -29,7 +29,7 @@ OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC = 1, 2, 4, 8
 EXPORTED = [
     "hab_init", "hab_shutdown", "hab_status_string", "hab_get_error",
     "hab_scene_upload", "hab_scene_release", "hab_scene_info", "hab_sensor_spec",
-    "hab_render", "hab_render_ex", "hab_render_batch",
+    "hab_render", "hab_render_ex", "hab_render_batch", "hab_render_noalloc",
     "hab_stepper_create", "hab_stepper_step", "hab_stepper_step_device", "hab_stepper_destroy",
     "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
@@ -147,6 +147,7 @@ def load():
             "hab_render_ex": [vp, vp, C.POINTER(Sensor), C.POINTER(Pose), u32, vp, vp, vp,
                               C.POINTER(RenderOpts), vp],
             "hab_render_batch": [vp, C.POINTER(View), u32, C.POINTER(RenderOpts), vp],
+            "hab_render_noalloc": [vp, vp, C.POINTER(Sensor), C.POINTER(Pose), u32, vp, vp, vp],
             "hab_stepper_create": [vp, C.POINTER(View), u32, C.POINTER(RenderOpts), vp,
                                    C.POINTER(vp)],
             "hab_stepper_step": [vp, C.POINTER(Pose), vp],

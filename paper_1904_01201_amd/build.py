@@ -19,8 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libhabmi.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "actuate.hip", "runtime.cpp", "abi.cpp", "stepper.cpp", "server.cpp",
-           "autotune.cpp"]
+SOURCES = ["kernels.hip", "actuate.hip", "noalloc.hip", "runtime.cpp", "abi.cpp", "stepper.cpp",
+           "server.cpp", "autotune.cpp"]
 ARCH = os.environ.get("HABMI_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -54,6 +54,12 @@ hab_status hab_init(int device, hab_context **out)
             delete ctx;
             return HAB_ERR_DEVICE;
         }
+        const hab_status na = noalloc_setup(ctx);
+        if (na != HAB_OK) {
+            (void)hipFree(ctx->err);
+            delete ctx;
+            return na;
+        }
         *out = ctx;
         return HAB_OK;
     });

@@ -13,6 +13,24 @@ static constexpr uint32_t kDefaultTile = 16;
 static constexpr uint64_t kIndexLimit = 1ull << 31; // per launch: survivors, bins, tiles
 
 static inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+// Stable sort that allocates nothing for short ranges (insertion sort; the
+// allocation-free render entry plans at most 256 views); longer ranges use
+// std::stable_sort.
+template <class It, class Cmp>
+static void stable_sort_views(It b, It e, Cmp less)
+{
+    if (e - b > 256) {
+        std::stable_sort(b, e, less);
+        return;
+    }
+    for (It i = b + (e > b ? 1 : 0); i < e; ++i) {
+        auto x = *i;
+        It j = i;
+        for (; j > b && less(x, *(j - 1)); --j) *j = *(j - 1);
+        *j = x;
+    }
+}
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------- workspace
@@ -77,6 +95,53 @@ hab_status Workspace::staging(size_t bytes, void **host, int *slot)
     }
     *host = s.host;
     return HAB_OK;
+}
+
+hab_status Workspace::reserve_staging(size_t bytes)
+{
+    for (int k = 0; k < kSlots; ++k) {
+        Slot &s = slots[k];
+        if (!s.ev) HAB_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+        if (s.cap >= bytes) continue;
+        if (s.pending) {
+            HAB_HIP(hipEventSynchronize(s.ev));
+            s.pending = false;
+        }
+        if (s.host) HAB_HIP(hipHostFree(s.host));
+        s.host = nullptr;
+        s.cap = 0;
+        if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess) {
+            s.host = nullptr;
+            (void)hipGetLastError();
+            return HAB_ERR_OUT_OF_MEMORY;
+        }
+        s.cap = bytes;
+    }
+    return HAB_OK;
+}
+
+hab_status Workspace::staging_reserved(size_t bytes, void **host, int *slot)
+{
+    Slot &s = slots[next];
+    if (!s.ev || !s.host || s.cap < bytes) return HAB_ERR_CAPACITY;
+    *slot = next;
+    next = (next + 1) % kSlots;
+    if (s.pending) {
+        HAB_HIP(hipEventSynchronize(s.ev));
+        s.pending = false;
+    }
+    *host = s.host;
+    return HAB_OK;
+}
+
+void Workspace::reserve_planning(uint32_t n, size_t desc_bytes)
+{
+    desc.reserve(desc_bytes);
+    dv.reserve(n);
+    for (int c = 0; c < 3; ++c) {
+        lview[c].reserve(n);
+        lpre[c].reserve(n);
+    }
 }
 
 // ---------------------------------------------------------------- validation
@@ -187,16 +252,21 @@ static inline uint32_t ts_log2(uint32_t ts) { return ts == 8 ? 3u : ts == 16 ? 4
 hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
                       const PlanOpts &o, Plan &plan, std::vector<uint8_t> &desc)
 {
-    (void)ws;
     if (n == 0 || n > kMaxViews) return HAB_ERR_INVALID_ARG;
     plan.n = n;
     plan.order.resize(n);
     std::iota(plan.order.begin(), plan.order.end(), 0u);
-    std::stable_sort(plan.order.begin(), plan.order.end(),
-                     [&](uint32_t a, uint32_t b) { return v[a].scene < v[b].scene; });
+    stable_sort_views(plan.order.begin(), plan.order.end(),
+                      [&](uint32_t a, uint32_t b) { return v[a].scene < v[b].scene; });
 
-    std::vector<DView> dv(n);
-    std::vector<uint32_t> lview[3], lpre[3];
+    // the workspace's buffers: no allocation once they have grown to n views
+    std::vector<DView> &dv = ws.dv;
+    dv.resize(n);
+    std::vector<uint32_t> *lview = ws.lview, *lpre = ws.lpre;
+    for (int c = 0; c < 3; ++c) {
+        lview[c].clear();
+        lpre[c].clear();
+    }
     uint64_t tile_total = 0, surv_total = 0, bin_total = 0, pair_total = 0;
     for (uint32_t k = 0; k < n; ++k) {
         const ViewReq &r = v[plan.order[k]];
@@ -254,8 +324,8 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     // the largest scenes (the longest tile lists) first so that their tiles
     // do not form the tail of the launch.
     for (int c = 0; c < 3; ++c) {
-        std::stable_sort(lview[c].begin(), lview[c].end(),
-                         [&](uint32_t a, uint32_t b) { return dv[a].T > dv[b].T; });
+        stable_sort_views(lview[c].begin(), lview[c].end(),
+                          [&](uint32_t a, uint32_t b) { return dv[a].T > dv[b].T; });
         uint32_t pre = 0;
         for (uint32_t k : lview[c]) {
             lpre[c].push_back(pre);
@@ -459,6 +529,23 @@ hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint3
             o2.covered = c[k].covered;
         }
     }
+    return HAB_OK;
+}
+
+hab_status stage_and_launch(hab_context *ctx, Workspace &ws, Plan &plan, void *arena, hipStream_t s,
+                            bool reserved)
+{
+    void *host;
+    int slot;
+    hab_status st = reserved ? ws.staging_reserved(plan.desc_bytes, &host, &slot)
+                             : ws.staging(plan.desc_bytes, &host, &slot);
+    if (st != HAB_OK) return st;
+    std::memcpy(host, ws.desc.data(), plan.desc_bytes);
+    HAB_HIP(hipMemcpyAsync(arena, host, plan.desc_bytes, hipMemcpyHostToDevice, s));
+    HAB_HIP(hipEventRecord(ws.slots[slot].ev, s));
+    ws.slots[slot].pending = true;
+    bind_plan(plan, arena, ctx->err);
+    HAB_HIP(launch_render(plan.L, s));
     return HAB_OK;
 }
 

@@ -109,12 +109,20 @@ struct Workspace {
     hipStream_t last_stream = nullptr;
     bool last_valid = false;
     // host-side planning buffers, kept to avoid reallocation
-    std::vector<ViewReq> sorted;
-    std::vector<uint32_t> order;
     std::vector<uint8_t> desc;
+    std::vector<DView> dv;
+    std::vector<uint32_t> lview[3], lpre[3];
     ~Workspace();
     hab_status ensure(size_t bytes);
     hab_status staging(size_t bytes, void **host, int *slot);
+    // Pinned slots of at least `bytes` each and their events, made now so
+    // that staging_reserved() never allocates.
+    hab_status reserve_staging(size_t bytes);
+    // The next slot if it holds `bytes` (else HAB_ERR_CAPACITY); waits for
+    // the slot's previous copy; allocates nothing.
+    hab_status staging_reserved(size_t bytes, void **host, int *slot);
+    // Planning buffers with room for n views (reserved, not resized).
+    void reserve_planning(uint32_t n, size_t desc_bytes);
 };
 
 // Everything one launch sequence needs, laid out in a workspace arena.
@@ -168,6 +176,13 @@ struct hab_context {
     habmi::Workspace act_ws;
     std::vector<const hab_nav *> act_last;
     size_t act_last_off = 0;
+    // hab_render_noalloc: the device's static scratch array (its address on
+    // this context's device), planning buffers and pinned staging reserved
+    // at hab_init
+    void *na_scratch = nullptr;
+    habmi::Workspace na_ws;
+    habmi::Plan na_plan;
+    std::vector<habmi::ViewReq> na_req;
 };
 
 struct hab_scene : habmi::Scene {};
@@ -190,6 +205,16 @@ void bind_plan(Plan &plan, void *arena, uint32_t *err);
 // fills them (caller order).
 hab_status render_views(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
                         const PlanOpts &o, hipStream_t s, hab_view_stats *stats);
+// Copy a planned descriptor block through a pinned staging slot to the
+// arena base, bind the plan there and enqueue its launch sequence (no
+// profiling events, no statistics).  `reserved`: take only a slot reserved
+// beforehand (allocates nothing).
+hab_status stage_and_launch(hab_context *ctx, Workspace &ws, Plan &plan, void *arena, hipStream_t s,
+                            bool reserved);
+// Reserve what hab_render_noalloc uses on ctx's device (called by hab_init
+// with that device current): the scratch array's address, planning buffers,
+// pinned staging.
+hab_status noalloc_setup(hab_context *ctx);
 // Split a request list into launch sequences that fit the limits and run
 // them all.
 hab_status render_all(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,

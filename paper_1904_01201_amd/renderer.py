@@ -232,6 +232,17 @@ class Context:
                                     poses.shape[0], _ptr(rgb), _ptr(depth), _stream_ptr(stream)),
                 "hab_render")
 
+    def render_noalloc(self, scene, sensor, poses, rgb=None, depth=None, stream=None):
+        """hab_render_noalloc: hab_render on the library's static scratch
+        array (no allocation in the call)."""
+        poses = np.asarray(poses, np.float32).reshape(-1, 12)
+        check_output("rgb", rgb, poses.shape[0], sensor)
+        check_output("depth", depth, poses.shape[0], sensor)
+        pc = B.poses_to_c(poses)
+        B.check(self.lib.hab_render_noalloc(self.h, C.c_void_p(scene.ptr), C.byref(sensor), pc,
+                                            poses.shape[0], _ptr(rgb), _ptr(depth), _stream_ptr(stream)),
+                "hab_render_noalloc")
+
     def make_views(self, items):
         """items: iterable of (scene, sensor, pose, rgb, depth, tri[, semantic
         [, noise_seed]]) with tensors or None.  Returns a ctypes View array

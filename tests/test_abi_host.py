@@ -86,6 +86,7 @@ def test_null_arguments(lib):
     assert lib.hab_get_error(None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_render(None, None, None, None, 0, None, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_render_batch(None, None, 0, None, None) == B.HAB_ERR_INVALID_ARG
+    assert lib.hab_render_noalloc(None, None, None, None, 0, None, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_stepper_step(None, None, None) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_profile_phases(None, 1) == B.HAB_ERR_INVALID_ARG
     assert lib.hab_stepper_step_device(None, None, None) == B.HAB_ERR_INVALID_ARG
