@@ -132,6 +132,9 @@ def other_workloads(ctx, a):
 NAV_HEIGHTS = (0.1, 1.5)   # cross-section heights of the agent's body (just above the floor; its top)
 
 
+CPU_SHARE = 16   # host CPUs per GPU on the measurement boxes
+
+
 def actuation_leg(ctx, w, a, hs):
     """The agent step before rendering: batched actuation with
     collide-and-slide for 16,384 agents per scene of the bench workload
@@ -525,7 +528,9 @@ def main():
     if not a.no_cpu_baseline and a.cpu_views > 0:
         import oracle
         from concurrent.futures import ThreadPoolExecutor
-        threads = max(1, min(16, os.cpu_count() or 1))
+        # the host's share for one GPU is 16 CPUs (a pool sized to the
+        # visible count could oversubscribe it); the count visible is reported
+        threads = max(1, min(CPU_SHARE, os.cpu_count() or 1))
         jobs = []
         for k in range(a.cpu_views):
             s_, e_ = divmod(k, E)
@@ -552,8 +557,27 @@ def main():
                          f"workload, one view per thread, {t_cpu:.1f}s wall, {c_cpu:.1f} CPU-s",
                "single_thread_value": round(n1 / t_one, 2),
                "single_thread_sample": f"first {n1} views (step 0), one thread, {t_one:.1f}s",
+               "host_cpus_visible": os.cpu_count(), "cpu_share_used": threads,
                "cpu_model": cpu_model()}
         log(f"cpu oracle: {cpu['value']} frames/s")
+        # the two plain-path workloads, timed in full on the same threads
+        full = {}
+        for name, wl, px in (("room_2k_128", configs.room_2k_128(), 128),
+                             ("apartment_200k_256", configs.apartment_200k_256(), 256)):
+            sc = wl.scenes[0]
+            views = wl.poses[:, 0]
+
+            def one_full(pose, sc=sc, px=px):
+                oracle.render_view(sc.positions, sc.colors, sc.indices, px, px, pose)
+
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                list(ex.map(one_full, views))
+            el = time.perf_counter() - t0
+            full[name] = {"frames_per_s": round(len(views) / el, 2), "views": len(views),
+                          "threads": threads, "wall_s": round(el, 2)}
+            log(f"cpu oracle {name}: {full[name]['frames_per_s']} frames/s ({len(views)} views)")
+        cpu["full_workloads"] = full
 
     res = {
         "metric": METRIC,

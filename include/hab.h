@@ -72,7 +72,10 @@ typedef enum {
     HAB_ERR_RANGE = 3,         /* pose/scene outside the fixed-point domain          */
     HAB_ERR_DEVICE = 4,        /* a HIP call failed                                  */
     HAB_ERR_NOT_READY = 5,     /* poll: the request has not completed yet            */
-    HAB_ERR_CAPACITY = 6       /* queue full, request over budget, or beyond a limit */
+    HAB_ERR_CAPACITY = 6,      /* queue full, request over budget, or beyond a limit */
+    HAB_ERR_CANCELLED = 7,     /* server: the request was cancelled before launch    */
+    HAB_ERR_TIMEOUT = 8,       /* server: the request was not launched by its deadline */
+    HAB_STATUS_MAX_ = 0x7FFFFFFF /* (not a status: makes every non-negative int a valid value) */
 } hab_status;
 
 #define HAB_NO_HIT 0xFFFFFFFFu
@@ -404,18 +407,43 @@ typedef struct {
 
 typedef struct {
     uint64_t submitted, completed, batches, rejected;
-    uint64_t peak_inflight_bytes;
+    uint64_t peak_inflight_bytes;   /* largest footprint of the batches in flight at once */
     uint32_t peak_batch;
+    uint32_t pad;
+    uint64_t cancelled, expired;    /* requests cancelled / timed out before launch */
+    uint64_t scratch_bytes;         /* device scratch the server holds (= memory_budget) */
 } hab_server_stats;
 
 /* Start the request loop (one host thread) on a context the caller then
- * no longer uses directly until hab_server_destroy. */
+ * no longer uses directly until hab_server_destroy.  The server's device
+ * scratch is one allocation of memory_budget bytes made here; every batch
+ * works in a region of it, so the budget bounds the memory held.
+ *
+ * Admission (deterministic, in arrival order): a request's footprint is an
+ * upper bound of its launch scratch (survivor and setup-record slots, tile
+ * lists, work items and partial results for its scene, sensor and tile
+ * size); a batch takes queued requests in order, among the first 64, while
+ * their summed footprint fits the largest free region of the scratch; a
+ * request passed over by 8 launched batches blocks those behind it until
+ * it is admitted (it waits at most for the batches in flight). */
 hab_status hab_server_create(hab_context *ctx, const hab_server_cfg *cfg, hab_server **out);
 /* Non-blocking: queue one view (its pointers must stay valid until the
- * request completes).  Returns a ticket. */
+ * request completes).  Returns a ticket.  HAB_ERR_CAPACITY when the queue
+ * is full or the request's footprint exceeds the budget. */
 hab_status hab_server_submit(hab_server *srv, const hab_view *view, uint64_t *ticket);
+/* As hab_server_submit with a deadline: a request not launched within
+ * timeout_us microseconds of submission is dropped and its ticket reports
+ * HAB_ERR_TIMEOUT (0: no deadline). */
+hab_status hab_server_submit_ex(hab_server *srv, const hab_view *view, uint32_t timeout_us,
+                                uint64_t *ticket);
+/* Cancel a queued request: HAB_OK (its ticket then reports
+ * HAB_ERR_CANCELLED); HAB_ERR_NOT_READY when it is already launched (it
+ * completes normally); HAB_ERR_INVALID_ARG for a ticket that is done,
+ * collected or unknown. */
+hab_status hab_server_cancel(hab_server *srv, uint64_t ticket);
 /* HAB_ERR_NOT_READY until the ticket's outputs are complete in device
- * memory; then HAB_OK and, if stats is non-NULL, its timestamps. */
+ * memory; then HAB_OK and, if stats is non-NULL, its timestamps (or the
+ * request's error: HAB_ERR_CANCELLED, HAB_ERR_TIMEOUT, a launch error). */
 hab_status hab_server_poll(hab_server *srv, uint64_t ticket, hab_request_stats *stats);
 hab_status hab_server_wait(hab_server *srv, uint64_t ticket, hab_request_stats *stats);
 hab_status hab_server_stats_get(hab_server *srv, hab_server_stats *out);
@@ -463,9 +491,26 @@ hab_status hab_selfcheck_reciprocal(hab_context *ctx, uint32_t lo_bits, uint32_t
  * later calls with opts->tile_size == 0 (and the stepper and server) use
  * them.  *chosen_tile_size / *chosen_bin_factor (may be NULL) receive the
  * first view's class's choice.  Renders on `stream` and synchronises it.
- * Results are identical for every choice. */
+ * Results are identical for every choice.
+ *
+ * With the environment variable HABMI_AUTOTUNE_CACHE naming a file, the
+ * context's whole table is written there (JSON: the GPU architecture and
+ * one {"class", "tile", "bin_factor"} entry per class, replaced atomically;
+ * HAB_ERR_INVALID_ARG if it cannot be written, the choices still made), and
+ * hab_init loads the entries saved for the same architecture. */
 hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint32_t num_views,
                         hipStream_t stream, uint32_t *chosen_tile_size, float *chosen_bin_factor);
+
+/* ---------------------------------------------------------- testing */
+/* For tests of failure handling: every device and pinned host allocation
+ * of the library goes through one place; after `after` more successful
+ * allocations every further one fails as if out of memory, until this is
+ * called with after < 0.  Process-wide. */
+hab_status hab_test_fail_alloc(int64_t after);
+/* Device and pinned host allocations of the library still held (count and
+ * bytes), process-wide: an entry point that fails must leave them as they
+ * were. */
+hab_status hab_test_live_allocations(uint64_t *count, uint64_t *bytes);
 
 #ifdef __cplusplus
 }

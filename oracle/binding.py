@@ -15,7 +15,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# ORACLE_SANITIZE=1: a build instrumented by AddressSanitizer and
+# UndefinedBehaviorSanitizer (liboracle_san.so), loaded with gcc's ASan
+# runtime preloaded, for the sanitizer runs of the oracle's own tests
+SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+LIB = os.path.join(HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 
 OR_OK = 0
 OR_ERR_INVALID_ARG = 1
@@ -24,6 +28,8 @@ NONE = 0xFFFFFFFF
 
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin",
           "-msse2", "-mfpmath=sse", "-fPIC", "-shared", "-Wall", "-Wextra"]
+if SANITIZE:
+    CFLAGS += ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
 
 
 class Stats(C.Structure):

@@ -8,10 +8,12 @@ it has not been built.
 """
 from .binding import (HabError, OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC, HAB_NO_HIT, HAB_OK,
                       HAB_ERR_INVALID_ARG, HAB_ERR_OUT_OF_MEMORY, HAB_ERR_RANGE,
-                      HAB_ERR_DEVICE, HAB_ERR_NOT_READY, HAB_ERR_CAPACITY, load, lib_path)
+                      HAB_ERR_DEVICE, HAB_ERR_NOT_READY, HAB_ERR_CAPACITY, HAB_ERR_CANCELLED,
+                      HAB_ERR_TIMEOUT, load, lib_path)
 from .renderer import Context, NavHandle, SceneHandle, Server, Stepper
 
 __all__ = ["Context", "NavHandle", "SceneHandle", "Server", "Stepper", "HabError", "OUT_RGB", "OUT_DEPTH", "OUT_TRI",
            "OUT_SEMANTIC",           "HAB_NO_HIT", "HAB_OK", "HAB_ERR_INVALID_ARG", "HAB_ERR_OUT_OF_MEMORY",
-           "HAB_ERR_RANGE", "HAB_ERR_DEVICE", "HAB_ERR_NOT_READY", "HAB_ERR_CAPACITY", "load",
+           "HAB_ERR_RANGE", "HAB_ERR_DEVICE", "HAB_ERR_NOT_READY", "HAB_ERR_CAPACITY",
+           "HAB_ERR_CANCELLED", "HAB_ERR_TIMEOUT", "load",
            "lib_path"]

@@ -14,7 +14,9 @@ import threading
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhabmi.so")
+# HABMI_LIBRARY names another build of this library (the sanitizer build of
+# the host runtime, for CPU tests); by default the one built next to this file
+LIB_PATH = os.environ.get("HABMI_LIBRARY") or os.path.join(HERE, "libhabmi.so")
 
 HAB_OK = 0
 HAB_ERR_INVALID_ARG = 1
@@ -23,6 +25,8 @@ HAB_ERR_RANGE = 3
 HAB_ERR_DEVICE = 4
 HAB_ERR_NOT_READY = 5
 HAB_ERR_CAPACITY = 6
+HAB_ERR_CANCELLED = 7
+HAB_ERR_TIMEOUT = 8
 HAB_NO_HIT = 0xFFFFFFFF
 OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC = 1, 2, 4, 8
 
@@ -31,11 +35,12 @@ EXPORTED = [
     "hab_scene_upload", "hab_scene_release", "hab_scene_info", "hab_sensor_spec",
     "hab_render", "hab_render_ex", "hab_render_batch", "hab_render_noalloc",
     "hab_stepper_create", "hab_stepper_step", "hab_stepper_step_device", "hab_stepper_destroy",
-    "hab_server_create", "hab_server_submit", "hab_server_poll", "hab_server_wait",
+    "hab_server_create", "hab_server_submit", "hab_server_submit_ex", "hab_server_cancel",
+    "hab_server_poll", "hab_server_wait",
     "hab_server_stats_get", "hab_server_destroy", "hab_autotune",
     "hab_profile_enable", "hab_profile_phases", "hab_profile_read",
     "hab_nav_upload", "hab_nav_from_scene", "hab_nav_segments", "hab_nav_free", "hab_nav_release",
-    "hab_actuate", "hab_selfcheck_reciprocal",
+    "hab_actuate", "hab_selfcheck_reciprocal", "hab_test_fail_alloc", "hab_test_live_allocations",
 ]
 ACT_STOP, ACT_FORWARD, ACT_LEFT, ACT_RIGHT = 0, 1, 2, 3
 PHASES = ["reset", "setup", "bin_count", "bin_scan", "bin_scatter", "raster8", "raster16",
@@ -98,7 +103,8 @@ class RequestStats(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("batches", C.c_uint64),
                 ("rejected", C.c_uint64), ("peak_inflight_bytes", C.c_uint64),
-                ("peak_batch", C.c_uint32)]
+                ("peak_batch", C.c_uint32), ("pad", C.c_uint32), ("cancelled", C.c_uint64),
+                ("expired", C.c_uint64), ("scratch_bytes", C.c_uint64)]
 
 
 class PhaseTimes(C.Structure):
@@ -155,6 +161,10 @@ def load():
             "hab_stepper_destroy": [vp],
             "hab_server_create": [vp, C.POINTER(ServerCfg), C.POINTER(vp)],
             "hab_server_submit": [vp, C.POINTER(View), C.POINTER(C.c_uint64)],
+            "hab_server_submit_ex": [vp, C.POINTER(View), u32, C.POINTER(C.c_uint64)],
+            "hab_server_cancel": [vp, C.c_uint64],
+            "hab_test_fail_alloc": [C.c_int64],
+            "hab_test_live_allocations": [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
             "hab_server_poll": [vp, C.c_uint64, C.POINTER(RequestStats)],
             "hab_server_wait": [vp, C.c_uint64, C.POINTER(RequestStats)],
             "hab_server_stats_get": [vp, C.POINTER(ServerStats)],

@@ -23,6 +23,9 @@ const char *hab_status_string(hab_status s)
     case HAB_ERR_DEVICE: return "device error";
     case HAB_ERR_NOT_READY: return "not ready";
     case HAB_ERR_CAPACITY: return "capacity exceeded";
+    case HAB_ERR_CANCELLED: return "cancelled";
+    case HAB_ERR_TIMEOUT: return "timed out";
+    case HAB_STATUS_MAX_: break;
     }
     return "unknown status";
 }
@@ -44,22 +47,22 @@ hab_status hab_init(int device, hab_context **out)
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
             ctx->cu_count = prop.multiProcessorCount;
         for (int c = 0; c < 3; ++c) ctx->raster_bpc[c] = raster_blocks_per_cu(8 << c);
-        if (hipMalloc(&ctx->err, 256) != hipSuccess) {
-            (void)hipGetLastError();
+        if (!dev_alloc((void **)&ctx->err, 256)) {
             delete ctx;
             return HAB_ERR_OUT_OF_MEMORY;
         }
         if (hipMemset(ctx->err, 0, 256) != hipSuccess) {
-            (void)hipFree(ctx->err);
+            dev_free(ctx->err);
             delete ctx;
             return HAB_ERR_DEVICE;
         }
         const hab_status na = noalloc_setup(ctx);
         if (na != HAB_OK) {
-            (void)hipFree(ctx->err);
-            delete ctx;
+            dev_free(ctx->err);
+            delete ctx;   // frees whatever the reservation got (its staging slots)
             return na;
         }
+        autotune_cache_load(ctx);
         *out = ctx;
         return HAB_OK;
     });
@@ -68,13 +71,13 @@ hab_status hab_init(int device, hab_context **out)
 // Device memory of a scene (every pointer may be null).
 static void free_scene_mem(Scene *s)
 {
-    (void)hipFree(s->tpos);
-    (void)hipFree(s->col);
-    (void)hipFree(s->idx);
-    (void)hipFree(s->cbox);
-    (void)hipFree(s->inst);
-    (void)hipFree(s->uv);
-    (void)hipFree(s->tex);
+    dev_free(s->tpos);
+    dev_free(s->col);
+    dev_free(s->idx);
+    dev_free(s->cbox);
+    dev_free(s->inst);
+    dev_free(s->uv);
+    dev_free(s->tex);
 }
 
 hab_status hab_shutdown(hab_context *ctx)
@@ -91,7 +94,7 @@ hab_status hab_shutdown(hab_context *ctx)
         release_navs(ctx);
         for (auto &ps : ctx->prof_sets)
             for (auto &e : ps.ev) (void)hipEventDestroy(e);
-        if (ctx->err) (void)hipFree(ctx->err);
+        if (ctx->err) dev_free(ctx->err);
         delete ctx;
         return HAB_OK;
     });
@@ -201,15 +204,11 @@ hab_status hab_scene_upload(hab_context *ctx, const hab_mesh_desc *m, hipStream_
             free_scene_mem(s);
             delete s;
         };
-        bool ok = hipMalloc((void **)&s->tpos, bp) == hipSuccess &&
-                  hipMalloc((void **)&s->col, bc) == hipSuccess &&
-                  hipMalloc((void **)&s->idx, bi) == hipSuccess &&
-                  hipMalloc((void **)&s->cbox, bb) == hipSuccess &&
-                  (!bs || hipMalloc((void **)&s->inst, bs) == hipSuccess) &&
-                  (!buv || hipMalloc((void **)&s->uv, buv) == hipSuccess) &&
-                  (!btex || hipMalloc((void **)&s->tex, btex) == hipSuccess);
+        bool ok = dev_alloc((void **)&s->tpos, bp) && dev_alloc((void **)&s->col, bc) &&
+                  dev_alloc((void **)&s->idx, bi) && dev_alloc((void **)&s->cbox, bb) &&
+                  (!bs || dev_alloc((void **)&s->inst, bs)) && (!buv || dev_alloc((void **)&s->uv, buv)) &&
+                  (!btex || dev_alloc((void **)&s->tex, btex));
         if (!ok) {
-            (void)hipGetLastError();
             drop();
             return HAB_ERR_OUT_OF_MEMORY;
         }
@@ -420,17 +419,30 @@ hab_status hab_selfcheck_reciprocal(hab_context *ctx, uint32_t lo_bits, uint32_t
         DeviceGuard g(ctx->device);
         if (!g.ok) return HAB_ERR_DEVICE;
         unsigned long long *d = nullptr;
-        HAB_HIP(hipMalloc(&d, sizeof *d));
+        if (!dev_alloc((void **)&d, sizeof *d)) return HAB_ERR_OUT_OF_MEMORY;
         unsigned long long h = 0;
         hipError_t e = hipMemsetAsync(d, 0, sizeof *d, stream);
         if (e == hipSuccess) e = launch_check_recip(lo_bits, hi_bits, d, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        (void)hipFree(d);
+        dev_free(d);
         if (e != hipSuccess) return HAB_ERR_DEVICE;
         *mismatches = h;
         return HAB_OK;
     });
+}
+
+hab_status hab_test_fail_alloc(int64_t after)
+{
+    alloc_fail_after(after < 0 ? -1 : after);
+    return HAB_OK;
+}
+
+hab_status hab_test_live_allocations(uint64_t *count, uint64_t *bytes)
+{
+    if (!count || !bytes) return HAB_ERR_INVALID_ARG;
+    alloc_live(count, bytes);
+    return HAB_OK;
 }
 
 }  // extern "C"

@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kActBlock) void k_nav_free(NavDesc D, const double2
 void release_navs(hab_context *ctx)
 {
     for (hab_nav *n : ctx->navs) {
-        (void)hipFree(n->mem);
+        dev_free(n->mem);
         delete n;
     }
     ctx->navs.clear();
@@ -498,8 +498,7 @@ static hab_status nav_build(hab_context *ctx, const float *segments, uint32_t nu
         n->device = ctx->device;
         n->n = num_segments;
         if (num_segments) {
-            if (hipMalloc(&n->mem, o_items + bitems) != hipSuccess) {
-                (void)hipGetLastError();
+            if (!dev_alloc(&n->mem, o_items + bitems)) {
                 delete n;
                 return HAB_ERR_OUT_OF_MEMORY;
             }
@@ -507,7 +506,7 @@ static hab_status nav_build(hab_context *ctx, const float *segments, uint32_t nu
             if (hipMemcpy(m, segments, bseg, hipMemcpyHostToDevice) != hipSuccess ||
                 hipMemcpy(m + o_start, start.data(), bstart, hipMemcpyHostToDevice) != hipSuccess ||
                 (bitems && hipMemcpy(m + o_items, items.data(), bitems, hipMemcpyHostToDevice) != hipSuccess)) {
-                (void)hipFree(n->mem);
+                dev_free(n->mem);
                 delete n;
                 return HAB_ERR_DEVICE;
             }
@@ -546,7 +545,7 @@ hab_status hab_nav_release(hab_context *ctx, hab_nav *nav)
         DeviceGuard g(ctx->device);
         // work that still reads the segments must finish first
         HAB_HIP(hipDeviceSynchronize());
-        (void)hipFree(nav->mem);
+        dev_free(nav->mem);
         ctx->navs.erase(it);
         delete nav;
         ctx->act_last.clear();
@@ -652,16 +651,13 @@ hab_status hab_nav_from_scene(hab_context *ctx, const hab_scene *scene, const do
             S.K = num_heights;
             const uint32_t nb = (T + kSliceBlock - 1) / kSliceBlock;
             uint32_t *dtot = nullptr;
-            if (hipMalloc(&dtot, 8ull * nb) != hipSuccess) {
-                (void)hipGetLastError();
-                return HAB_ERR_OUT_OF_MEMORY;
-            }
+            if (!dev_alloc((void **)&dtot, 8ull * nb)) return HAB_ERR_OUT_OF_MEMORY;
             uint32_t *dbase = dtot + nb;
             std::vector<uint32_t> tot(nb), base(nb);
             float4 *dseg = nullptr;
             auto fail = [&](hab_status st) {
-                (void)hipFree(dtot);
-                if (dseg) (void)hipFree(dseg);
+                dev_free(dtot);
+                if (dseg) dev_free(dseg);
                 return st;
             };
             hipLaunchKernelGGL(k_slice_count, dim3(nb), dim3(kSliceBlock), 0, stream, scene->tpos, T, S, dtot);
@@ -676,10 +672,7 @@ hab_status hab_nav_from_scene(hab_context *ctx, const hab_scene *scene, const do
             }
             if (nseg >= (1ull << 31)) return fail(HAB_ERR_CAPACITY);
             if (nseg) {
-                if (hipMalloc(&dseg, 16ull * nseg) != hipSuccess) {
-                    (void)hipGetLastError();
-                    return fail(HAB_ERR_OUT_OF_MEMORY);
-                }
+                if (!dev_alloc((void **)&dseg, 16ull * nseg)) return fail(HAB_ERR_OUT_OF_MEMORY);
                 segs.resize(4ull * nseg);
                 if (hipMemcpyAsync(dbase, base.data(), 4ull * nb, hipMemcpyHostToDevice, stream) != hipSuccess)
                     return fail(HAB_ERR_DEVICE);

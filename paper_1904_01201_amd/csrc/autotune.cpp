@@ -6,9 +6,20 @@
 // more than 2%.  A candidate's time is the fastest of kReps renders.  The
 // choice cannot change any output (the rendering definition does not
 // depend on tiling or capacity).
+//
+// Persistent table: with HABMI_AUTOTUNE_CACHE naming a file, hab_init
+// loads the choices made earlier on the same GPU architecture and
+// hab_autotune writes the context's whole table back (JSON, one class per
+// line, replaced atomically), so later processes skip the tuning.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -61,7 +72,83 @@ hab_status time_batch(hab_context *ctx, std::vector<ViewReq> &req, hipStream_t s
     return HAB_OK;
 }
 
+std::string device_arch(int device)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t colon = a.find(':');   // drop feature flags (":sramecc+:xnack-")
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+const char *cache_path()
+{
+    const char *p = getenv("HABMI_AUTOTUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+// Write the context's table (tmp file + rename); false on an I/O error.
+bool cache_save(hab_context *ctx, const char *path)
+{
+    std::vector<Tuned> t;
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        t = ctx->tuned;
+    }
+    std::sort(t.begin(), t.end(), [](const Tuned &a, const Tuned &b) { return a.key < b.key; });
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fprintf(f, "{\"arch\": \"%s\", \"entries\": [\n", device_arch(ctx->device).c_str());
+    for (size_t k = 0; k < t.size(); ++k)
+        fprintf(f, "  {\"class\": %u, \"tile\": %u, \"bin_factor\": %.9g}%s\n", t[k].key, t[k].ts,
+                (double)t[k].bin_factor, k + 1 < t.size() ? "," : "");
+    fprintf(f, "]}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path) != 0) {
+        (void)remove(tmp.c_str());
+        return false;
+    }
+    return true;
+}
+
 }  // namespace
+
+namespace habmi {
+
+// Entries of the file written by cache_save for this context's
+// architecture; anything else (another architecture, a malformed line, an
+// invalid choice) is skipped.
+void autotune_cache_load(hab_context *ctx)
+{
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    bool arch_ok = false;
+    const std::string arch = device_arch(ctx->device);
+    std::vector<Tuned> got;
+    while (fgets(line, sizeof line, f)) {
+        char a[128];
+        if (sscanf(line, " {\"arch\": \"%127[^\"]\"", a) == 1) arch_ok = arch == a;
+        unsigned key = 0, ts = 0;
+        double bf = 0.0;
+        if (sscanf(line, " {\"class\": %u, \"tile\": %u, \"bin_factor\": %lf}", &key, &ts, &bf) == 3 &&
+            (ts == 8 || ts == 16 || ts == 32) && (bf == 1.0 || bf == 2.0 || bf == 4.0))
+            got.push_back(Tuned{key, ts, (float)bf});
+    }
+    fclose(f);
+    if (!arch_ok) return;
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    for (const Tuned &t : got) {
+        auto it = std::find_if(ctx->tuned.begin(), ctx->tuned.end(), [&](const Tuned &u) { return u.key == t.key; });
+        if (it != ctx->tuned.end()) *it = t;
+        else ctx->tuned.push_back(t);
+    }
+}
+
+}  // namespace habmi
 
 extern "C" hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint32_t n,
                                    hipStream_t stream, uint32_t *chosen_ts, float *chosen_bf)
@@ -127,6 +214,8 @@ extern "C" hab_status hab_autotune(hab_context *ctx, const hab_view *views, uint
             const Tuned &first = best[class_key(req[0].scene, &req[0].sensor)];
             if (chosen_ts) *chosen_ts = first.ts;
             if (chosen_bf) *chosen_bf = first.bin_factor;
+            if (const char *path = cache_path())
+                if (!cache_save(ctx, path)) rc = HAB_ERR_INVALID_ARG;   // tuned, but the file could not be written
         }
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <unordered_map>
 
 namespace habmi {
 
@@ -33,16 +34,91 @@ static void stable_sort_views(It b, It e, Cmp less)
 }
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------- allocation
+namespace {
+std::mutex g_alloc_mu;
+int64_t g_fail_after = -1;                      // allocations left before one fails (-1: never)
+std::unordered_map<void *, size_t> g_live;      // pointer -> bytes
+
+// After g_fail_after more successes every allocation fails, until reset.
+bool inject_failure()
+{
+    if (g_fail_after < 0) return false;
+    if (g_fail_after == 0) return true;
+    --g_fail_after;
+    return false;
+}
+}  // namespace
+
+bool dev_alloc(void **p, size_t bytes)
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    *p = nullptr;
+    if (inject_failure()) return false;
+    if (hipMalloc(p, std::max<size_t>(bytes, 1)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    g_live[*p] = bytes;
+    return true;
+}
+
+void dev_free(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_live.erase(p);
+    (void)hipFree(p);
+}
+
+bool pinned_alloc(void **p, size_t bytes)
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    *p = nullptr;
+    if (inject_failure()) return false;
+    if (hipHostMalloc(p, std::max<size_t>(bytes, 1), hipHostMallocDefault) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    g_live[*p] = bytes;
+    return true;
+}
+
+void pinned_free(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_live.erase(p);
+    (void)hipHostFree(p);
+}
+
+void alloc_fail_after(int64_t n)
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_fail_after = n;
+}
+
+void alloc_live(uint64_t *count, uint64_t *bytes)
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    uint64_t b = 0;
+    for (const auto &e : g_live) b += e.second;
+    *count = g_live.size();
+    *bytes = b;
+}
+
 // ---------------------------------------------------------------- workspace
 Workspace::~Workspace()
 {
     if (has_done) (void)hipEventSynchronize(done);
     for (auto &s : slots) {
         if (s.pending) (void)hipEventSynchronize(s.ev);
-        if (s.host) (void)hipHostFree(s.host);
+        if (s.host) pinned_free(s.host);
         if (s.ev) (void)hipEventDestroy(s.ev);
     }
-    if (arena) (void)hipFree(arena);
+    if (arena && !external) dev_free(arena);
     if (done) (void)hipEventDestroy(done);
 }
 
@@ -50,21 +126,17 @@ hab_status Workspace::ensure(size_t bytes)
 {
     if (!done) HAB_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
     if (bytes <= cap) return HAB_OK;
+    if (external) return HAB_ERR_CAPACITY;
     if (has_done) HAB_HIP(hipEventSynchronize(done));
+    const size_t old = cap;
     if (arena) {
-        HAB_HIP(hipFree(arena));
+        dev_free(arena);
         arena = nullptr;
         cap = 0;
     }
-    size_t want = std::max(bytes, cap + cap / 2);
-    if (hipMalloc(&arena, want) != hipSuccess) {
-        arena = nullptr;
-        (void)hipGetLastError();
-        if (hipMalloc(&arena, bytes) != hipSuccess) {
-            arena = nullptr;
-            (void)hipGetLastError();
-            return HAB_ERR_OUT_OF_MEMORY;
-        }
+    size_t want = std::max(bytes, old + old / 2);
+    if (!dev_alloc(&arena, want)) {
+        if (!dev_alloc(&arena, bytes)) return HAB_ERR_OUT_OF_MEMORY;
         want = bytes;
     }
     cap = want;
@@ -82,15 +154,11 @@ hab_status Workspace::staging(size_t bytes, void **host, int *slot)
         s.pending = false;
     }
     if (s.cap < bytes) {
-        if (s.host) HAB_HIP(hipHostFree(s.host));
+        if (s.host) pinned_free(s.host);
         s.host = nullptr;
         s.cap = 0;
         size_t want = std::max(bytes, (size_t)64 << 10);
-        if (hipHostMalloc(&s.host, want, hipHostMallocDefault) != hipSuccess) {
-            s.host = nullptr;
-            (void)hipGetLastError();
-            return HAB_ERR_OUT_OF_MEMORY;
-        }
+        if (!pinned_alloc(&s.host, want)) return HAB_ERR_OUT_OF_MEMORY;
         s.cap = want;
     }
     *host = s.host;
@@ -107,14 +175,10 @@ hab_status Workspace::reserve_staging(size_t bytes)
             HAB_HIP(hipEventSynchronize(s.ev));
             s.pending = false;
         }
-        if (s.host) HAB_HIP(hipHostFree(s.host));
+        if (s.host) pinned_free(s.host);
         s.host = nullptr;
         s.cap = 0;
-        if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess) {
-            s.host = nullptr;
-            (void)hipGetLastError();
-            return HAB_ERR_OUT_OF_MEMORY;
-        }
+        if (!pinned_alloc(&s.host, bytes)) return HAB_ERR_OUT_OF_MEMORY;
         s.cap = bytes;
     }
     return HAB_OK;

@@ -20,6 +20,17 @@ namespace habmi {
         if (e_ != hipSuccess) return HAB_ERR_DEVICE; \
     } while (0)
 
+// Every device and pinned host allocation of the library goes through
+// these, so that a test can make an allocation fail on purpose
+// (hab_test_fail_alloc) and count what is still allocated
+// (hab_test_live_allocations).  false: out of memory (nothing allocated).
+bool dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
+bool pinned_alloc(void **p, size_t bytes);
+void pinned_free(void *p);
+void alloc_fail_after(int64_t n);                // n < 0: no injected failure
+void alloc_live(uint64_t *count, uint64_t *bytes);
+
 // Make a context's device current for the duration of a call.
 struct DeviceGuard {
     int prev = -1;
@@ -95,6 +106,7 @@ struct Workspace {
     int device = 0;
     void *arena = nullptr;
     size_t cap = 0;
+    bool external = false;      // arena owned by someone else (a server pool region): never reallocated
     struct Slot {
         void *host = nullptr;
         size_t cap = 0;
@@ -215,6 +227,9 @@ hab_status stage_and_launch(hab_context *ctx, Workspace &ws, Plan &plan, void *a
 // with that device current): the scratch array's address, planning buffers,
 // pinned staging.
 hab_status noalloc_setup(hab_context *ctx);
+// Load the autotune choices saved in the HABMI_AUTOTUNE_CACHE file for this
+// context's GPU architecture (nothing when unset, missing or another one).
+void autotune_cache_load(hab_context *ctx);
 // Split a request list into launch sequences that fit the limits and run
 // them all.
 hab_status render_all(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,

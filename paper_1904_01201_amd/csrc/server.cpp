@@ -3,9 +3,13 @@
 // request thread admits them by memory footprint and packs them into
 // batches that run on `num_streams` HIP streams at once (continuous
 // batching: requests that arrive while batches are on the device are
-// admitted as soon as a stream and memory free up).  Each batch is an
-// ordinary launch sequence, so a result is bitwise the same alone and in
-// any mix.  Latency is stamped at submit, launch and observed completion.
+// admitted as soon as a stream and memory free up).  The server's device
+// scratch is one pool of memory_budget bytes allocated at creation; each
+// launched batch works in a region of it (admission.h), so the budget
+// bounds the memory actually held.  Each batch is an ordinary launch
+// sequence, so a result is bitwise the same alone and in any mix.  Latency
+// is stamped at submit, launch and observed completion.  Queued requests
+// can be cancelled, and time out at their deadline.
 #include <time.h>
 
 #include <algorithm>
@@ -19,6 +23,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admission.h"
 #include "runtime.h"
 
 using namespace habmi;
@@ -36,20 +41,19 @@ struct Req {
     uint64_t ticket;
     ViewReq view;
     uint64_t submit_ns;
-    uint64_t bytes;    // admission footprint (upper bound of its scratch)
 };
 
 struct Batch {
     std::vector<Req> reqs;
     hipEvent_t ev = nullptr;
-    int slot = -1;
-    uint64_t bytes = 0;
+    uint64_t offset = 0, bytes = 0;   // region of the scratch pool
     uint64_t launch_ns = 0;
     uint32_t id = 0;
     bool active = false;
 };
 
-constexpr uint32_t kSkipAhead = 64;   // queued requests a blocked head may be overtaken by
+constexpr uint32_t kSkipAhead = 64;   // queued requests a batch may look at
+constexpr uint32_t kMaxSkips = 8;     // batches that may pass one request over
 
 }  // namespace
 
@@ -59,15 +63,16 @@ struct hab_server {
     std::vector<Workspace *> ws;
     std::vector<hipStream_t> streams;
     std::vector<Batch> slots;
+    void *pool = nullptr;             // memory_budget bytes of device scratch
     std::thread th;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Req> queue;
+    Admission *adm = nullptr;
+    std::unordered_map<uint64_t, Req> queued;   // requests not launched yet
     std::unordered_map<uint64_t, hab_request_stats> done;
     std::unordered_map<uint64_t, hab_status> failed;
     std::unordered_map<uint64_t, uint8_t> pending;   // queued or in flight
     uint64_t next_ticket = 1;
-    uint64_t inflight_bytes = 0;
     uint32_t next_batch = 0;
     bool stop = false;
     hab_server_stats st{};
@@ -80,40 +85,30 @@ static uint64_t req_bytes(hab_server *s, const ViewReq &v)
     return footprint(&v, 1, o, s->ctx).arena_bytes;
 }
 
-static void complete(hab_server *s, Batch &b)
+// Retire a batch (caller holds the lock): results or an error per ticket,
+// its pool region returned.
+static void retire(hab_server *s, Batch &b, hab_status e, uint64_t t)
 {
-    const uint64_t t = now_ns();
-    std::lock_guard<std::mutex> g(s->mu);
     for (const Req &r : b.reqs) {
-        hab_request_stats rs;
-        rs.submit_ns = r.submit_ns;
-        rs.launch_ns = b.launch_ns;
-        rs.done_ns = t;
-        rs.batch_size = (uint32_t)b.reqs.size();
-        rs.batch_id = b.id;
-        s->done[r.ticket] = rs;
+        if (e == HAB_OK) {
+            hab_request_stats rs;
+            rs.submit_ns = r.submit_ns;
+            rs.launch_ns = b.launch_ns;
+            rs.done_ns = t;
+            rs.batch_size = (uint32_t)b.reqs.size();
+            rs.batch_id = b.id;
+            s->done[r.ticket] = rs;
+        } else {
+            s->failed[r.ticket] = e;
+        }
         s->pending.erase(r.ticket);
     }
-    s->st.completed += b.reqs.size();
-    s->inflight_bytes -= b.bytes;
-    b.bytes = 0;
+    if (e == HAB_OK) s->st.completed += b.reqs.size();
+    else s->loop_error = e;
+    s->adm->release(b.offset, b.bytes);
+    b.offset = b.bytes = 0;
     b.reqs.clear();
     b.active = false;
-    s->cv_done.notify_all();
-}
-
-static void fail_batch(hab_server *s, Batch &b, hab_status e)
-{
-    std::lock_guard<std::mutex> g(s->mu);
-    for (const Req &r : b.reqs) {
-        s->failed[r.ticket] = e;
-        s->pending.erase(r.ticket);
-    }
-    s->inflight_bytes -= b.bytes;
-    b.bytes = 0;
-    b.reqs.clear();
-    b.active = false;
-    s->loop_error = e;
     s->cv_done.notify_all();
 }
 
@@ -121,77 +116,86 @@ static void run_loop(hab_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
     std::vector<ViewReq> vr;
+    std::vector<uint64_t> gone;
+    Admission::Batch ab;
+    const uint64_t hold_ns = 1000ull * s->cfg.max_wait_us;
     for (;;) {
         // 1. retire finished batches
         for (Batch &b : s->slots) {
             if (!b.active) continue;
             const hipError_t q = hipEventQuery(b.ev);
-            if (q == hipSuccess) complete(s, b);
-            else if (q != hipErrorNotReady) fail_batch(s, b, HAB_ERR_DEVICE);
+            if (q == hipErrorNotReady) continue;
+            const uint64_t t = now_ns();
+            std::lock_guard<std::mutex> g(s->mu);
+            retire(s, b, q == hipSuccess ? HAB_OK : HAB_ERR_DEVICE, t);
         }
-        // 2. admit and launch on every free stream
+        // 2. queued requests past their deadline
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            gone.clear();
+            s->adm->expire(now_ns(), gone);
+            for (uint64_t tk : gone) {
+                s->queued.erase(tk);
+                s->pending.erase(tk);
+                s->failed[tk] = HAB_ERR_TIMEOUT;
+                s->st.expired += 1;
+            }
+            if (!gone.empty()) s->cv_done.notify_all();
+        }
+        // 3. admit and launch on every free stream
         bool launched = false;
         for (size_t k = 0; k < s->slots.size(); ++k) {
             Batch &b = s->slots[k];
             if (b.active) continue;
             {
-                std::unique_lock<std::mutex> g(s->mu);
-                if (s->queue.empty()) break;
-                // optionally hold a partial batch back to let it fill, up to
-                // max_wait_us after its oldest request arrived
-                if (s->cfg.max_wait_us && s->queue.size() < s->cfg.max_batch && !s->stop &&
-                    now_ns() - s->queue.front().submit_ns < 1000ull * s->cfg.max_wait_us)
-                    break;
-                b.bytes = 0;
+                std::lock_guard<std::mutex> g(s->mu);
+                if (!s->adm->next(now_ns(), hold_ns, s->stop, ab)) break;
                 b.reqs.clear();
-                uint64_t room = s->cfg.memory_budget - s->inflight_bytes;
-                uint32_t scanned = 0;
-                for (auto it = s->queue.begin();
-                     it != s->queue.end() && b.reqs.size() < s->cfg.max_batch && scanned < kSkipAhead;) {
-                    ++scanned;
-                    if (it->bytes <= room) {
-                        room -= it->bytes;
-                        b.bytes += it->bytes;
-                        b.reqs.push_back(*it);
-                        it = s->queue.erase(it);
-                    } else {
-                        ++it;
-                    }
+                for (const AdmReq &a : ab.reqs) {
+                    auto it = s->queued.find(a.ticket);
+                    b.reqs.push_back(it->second);
+                    s->queued.erase(it);
                 }
-                if (b.reqs.empty()) break;   // nothing fits until memory is released
-                s->inflight_bytes += b.bytes;
-                s->st.peak_inflight_bytes = std::max(s->st.peak_inflight_bytes, s->inflight_bytes);
+                b.offset = ab.offset;
+                b.bytes = ab.size;
+                s->st.peak_inflight_bytes = std::max(s->st.peak_inflight_bytes, s->adm->in_use());
                 s->st.peak_batch = std::max(s->st.peak_batch, (uint32_t)b.reqs.size());
                 s->st.batches += 1;
                 b.id = s->next_batch++;
             }
             vr.clear();
             for (const Req &r : b.reqs) vr.push_back(r.view);
-            b.slot = (int)k;
             b.launch_ns = now_ns();
+            // the batch's region of the pool is its workspace arena
+            Workspace &w = *s->ws[k];
+            w.arena = static_cast<char *>(s->pool) + b.offset;
+            w.cap = b.bytes;
             PlanOpts o;
-            hab_status e = render_all(s->ctx, *s->ws[k], vr.data(), (uint32_t)vr.size(), o,
-                                      s->streams[k], nullptr);
+            hab_status e = render_all(s->ctx, w, vr.data(), (uint32_t)vr.size(), o, s->streams[k], nullptr);
             if (e == HAB_OK && hipEventRecord(b.ev, s->streams[k]) != hipSuccess) e = HAB_ERR_DEVICE;
             if (e != HAB_OK) {
-                fail_batch(s, b, e);
+                // the stream may still be running earlier work on this
+                // region: wait before the region goes back to the pool
+                (void)hipStreamSynchronize(s->streams[k]);
+                std::lock_guard<std::mutex> g(s->mu);
+                retire(s, b, e, now_ns());
                 continue;
             }
             b.active = true;
             launched = true;
         }
-        // 3. exit or wait for work / completions
+        // 4. exit or wait for work / completions
         bool any_active = false;
         for (const Batch &b : s->slots) any_active |= b.active;
         std::unique_lock<std::mutex> g(s->mu);
-        if (s->stop && s->queue.empty() && !any_active) break;
+        if (s->stop && s->adm->queued() == 0 && !any_active) break;
         if (!launched) {
-            if (any_active || !s->queue.empty()) {
+            if (any_active || s->adm->queued() != 0) {
                 g.unlock();
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
             } else {
                 s->cv_work.wait_for(g, std::chrono::milliseconds(5),
-                                    [&] { return s->stop || !s->queue.empty(); });
+                                    [&] { return s->stop || s->adm->queued() != 0; });
             }
         }
     }
@@ -199,12 +203,27 @@ static void run_loop(hab_server *s)
 
 extern "C" {
 
+static void destroy_server(hab_server *s)
+{
+    for (size_t k = 0; k < s->streams.size(); ++k) {
+        (void)hipStreamSynchronize(s->streams[k]);
+        (void)hipStreamDestroy(s->streams[k]);
+    }
+    for (Workspace *w : s->ws) delete w;
+    for (Batch &b : s->slots)
+        if (b.ev) (void)hipEventDestroy(b.ev);
+    if (s->pool) dev_free(s->pool);
+    delete s->adm;
+    delete s;
+}
+
 hab_status hab_server_create(hab_context *ctx, const hab_server_cfg *cfg, hab_server **out)
 {
     if (!ctx || !out) return HAB_ERR_INVALID_ARG;
     *out = nullptr;
+    hab_server *s = nullptr;
     try {
-        hab_server *s = new hab_server();
+        s = new hab_server();
         s->ctx = ctx;
         hab_server_cfg c{};
         if (cfg) c = *cfg;
@@ -215,54 +234,67 @@ hab_status hab_server_create(hab_context *ctx, const hab_server_cfg *cfg, hab_se
         if (c.memory_budget == 0) c.memory_budget = 8ull << 30;
         if (c.max_queue == 0) c.max_queue = 65536;
         s->cfg = c;
-        int prev = -1;
-        (void)hipGetDevice(&prev);
-        if (hipSetDevice(ctx->device) != hipSuccess) {
-            delete s;
+        s->adm = new Admission(c.memory_budget, c.max_queue, c.max_batch, kSkipAhead, kMaxSkips);
+        DeviceGuard g(ctx->device);
+        if (!g.ok) {
+            destroy_server(s);
             return HAB_ERR_DEVICE;
         }
+        if (!dev_alloc(&s->pool, c.memory_budget)) {
+            destroy_server(s);
+            return HAB_ERR_OUT_OF_MEMORY;
+        }
+        s->st.scratch_bytes = c.memory_budget;
         s->slots.resize(c.num_streams);
         for (uint32_t k = 0; k < c.num_streams; ++k) {
             hipStream_t st = nullptr;
-            hipEvent_t ev = nullptr;
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                for (auto x : s->streams) (void)hipStreamDestroy(x);
-                delete s;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                destroy_server(s);
                 return HAB_ERR_DEVICE;
             }
             s->streams.push_back(st);
-            s->slots[k].ev = ev;
+            if (hipEventCreateWithFlags(&s->slots[k].ev, hipEventDisableTiming) != hipSuccess) {
+                s->slots[k].ev = nullptr;
+                destroy_server(s);
+                return HAB_ERR_DEVICE;
+            }
             Workspace *w = new Workspace();
             w->device = ctx->device;
+            w->external = true;   // its arena is a region of the pool
             s->ws.push_back(w);
         }
-        if (prev >= 0) (void)hipSetDevice(prev);
         s->th = std::thread(run_loop, s);
         *out = s;
         return HAB_OK;
     } catch (const std::bad_alloc &) {
+        if (s) destroy_server(s);
         return HAB_ERR_OUT_OF_MEMORY;
     }
 }
 
-hab_status hab_server_submit(hab_server *s, const hab_view *view, uint64_t *ticket)
+hab_status hab_server_submit_ex(hab_server *s, const hab_view *view, uint32_t timeout_us, uint64_t *ticket)
 {
     if (!s || !view || !ticket) return HAB_ERR_INVALID_ARG;
     try {
         Req r;
         hab_status e = to_view_req(*view, r.view);
         if (e != HAB_OK) return e;
-        r.bytes = req_bytes(s, r.view);
+        AdmReq a;
+        a.bytes = req_bytes(s, r.view);
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stop) return HAB_ERR_INVALID_ARG;
-        if (r.bytes > s->cfg.memory_budget || s->queue.size() >= s->cfg.max_queue) {
+        a.ticket = s->next_ticket;
+        a.submit_ns = now_ns();
+        a.deadline_ns = timeout_us ? a.submit_ns + 1000ull * timeout_us : 0;
+        const Admission::Submit q = s->adm->submit(a);
+        if (q != Admission::kQueued) {
             s->st.rejected += 1;
             return HAB_ERR_CAPACITY;
         }
-        r.ticket = s->next_ticket++;
-        r.submit_ns = now_ns();
-        s->queue.push_back(r);
+        r.ticket = a.ticket;
+        r.submit_ns = a.submit_ns;
+        s->next_ticket += 1;
+        s->queued.emplace(r.ticket, r);
         s->pending[r.ticket] = 1;
         s->st.submitted += 1;
         *ticket = r.ticket;
@@ -271,6 +303,27 @@ hab_status hab_server_submit(hab_server *s, const hab_view *view, uint64_t *tick
     } catch (const std::bad_alloc &) {
         return HAB_ERR_OUT_OF_MEMORY;
     }
+}
+
+hab_status hab_server_submit(hab_server *s, const hab_view *view, uint64_t *ticket)
+{
+    return hab_server_submit_ex(s, view, 0, ticket);
+}
+
+hab_status hab_server_cancel(hab_server *s, uint64_t ticket)
+{
+    if (!s) return HAB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->adm->cancel(ticket)) {
+        s->queued.erase(ticket);
+        s->pending.erase(ticket);
+        s->failed[ticket] = HAB_ERR_CANCELLED;
+        s->st.cancelled += 1;
+        s->cv_done.notify_all();
+        return HAB_OK;
+    }
+    // launched (it completes), or unknown / already collected
+    return s->pending.count(ticket) ? HAB_ERR_NOT_READY : HAB_ERR_INVALID_ARG;
 }
 
 static hab_status take(hab_server *s, uint64_t ticket, hab_request_stats *out)
@@ -326,17 +379,8 @@ hab_status hab_server_destroy(hab_server *s)
         s->cv_work.notify_all();
     }
     if (s->th.joinable()) s->th.join();
-    int prev = -1;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(s->ctx->device);
-    for (size_t k = 0; k < s->streams.size(); ++k) {
-        (void)hipStreamSynchronize(s->streams[k]);
-        delete s->ws[k];
-        (void)hipStreamDestroy(s->streams[k]);
-        (void)hipEventDestroy(s->slots[k].ev);
-    }
-    if (prev >= 0) (void)hipSetDevice(prev);
-    delete s;
+    DeviceGuard g(s->ctx->device);
+    destroy_server(s);
     return HAB_OK;
 }
 

@@ -56,13 +56,13 @@ static void destroy(hab_stepper *st)
         if (st->exec[b]) (void)hipGraphExecDestroy(st->exec[b]);
         if (st->exec_dev[b]) (void)hipGraphExecDestroy(st->exec_dev[b]);
         if (st->ev[b]) (void)hipEventDestroy(st->ev[b]);
-        if (st->host[b]) (void)hipHostFree(st->host[b]);
+        if (st->host[b]) pinned_free(st->host[b]);
     }
     if (st->has_last) (void)hipEventSynchronize(st->last);
     if (st->last) (void)hipEventDestroy(st->last);
     if (st->cap) (void)hipStreamDestroy(st->cap);
-    if (st->arena) (void)hipFree(st->arena);
-    if (st->dorder) (void)hipFree(st->dorder);
+    if (st->arena) dev_free(st->arena);
+    if (st->dorder) dev_free(st->dorder);
     delete st;
 }
 
@@ -98,16 +98,9 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
             return e;
         };
         if (s != HAB_OK) return fail(s);
-        if (hipMalloc(&st->arena, st->plan.arena_bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            st->arena = nullptr;
-            return fail(HAB_ERR_OUT_OF_MEMORY);
-        }
+        if (!dev_alloc(&st->arena, st->plan.arena_bytes)) return fail(HAB_ERR_OUT_OF_MEMORY);
         bind_plan(st->plan, st->arena, ctx->err);
-        if (hipMalloc((void **)&st->dorder, 4ull * n) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(HAB_ERR_OUT_OF_MEMORY);
-        }
+        if (!dev_alloc((void **)&st->dorder, 4ull * n)) return fail(HAB_ERR_OUT_OF_MEMORY);
         if (hipMemcpy(st->dorder, st->plan.order.data(), 4ull * n, hipMemcpyHostToDevice) != hipSuccess)
             return fail(HAB_ERR_DEVICE);
         if (hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess)
@@ -115,11 +108,7 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
         if (hipEventCreateWithFlags(&st->last, hipEventDisableTiming) != hipSuccess)
             return fail(HAB_ERR_DEVICE);
         for (int b = 0; b < 2; ++b) {
-            if (hipHostMalloc(&st->host[b], st->plan.desc_bytes, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                st->host[b] = nullptr;
-                return fail(HAB_ERR_OUT_OF_MEMORY);
-            }
+            if (!pinned_alloc(&st->host[b], st->plan.desc_bytes)) return fail(HAB_ERR_OUT_OF_MEMORY);
             std::memcpy(st->host[b], st->desc.data(), st->plan.desc_bytes);
             if (hipEventCreateWithFlags(&st->ev[b], hipEventDisableTiming) != hipSuccess)
                 return fail(HAB_ERR_DEVICE);

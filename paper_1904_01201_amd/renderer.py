@@ -458,7 +458,7 @@ class Server:
         self._keep = {}
 
     def submit(self, scene, sensor, pose, rgb=None, depth=None, tri=None, semantic=None,
-               noise_seed=0) -> int:
+               noise_seed=0, timeout_us=0) -> int:
         check_output("rgb", rgb, 1, sensor)
         check_output("depth", depth, 1, sensor)
         check_output("tri", tri, 1, sensor)
@@ -473,7 +473,8 @@ class Server:
         v.out_semantic = None if semantic is None else int(semantic.data_ptr())
         v.noise_seed = int(noise_seed)
         t = C.c_uint64()
-        B.check(self.lib.hab_server_submit(self.h, C.byref(v), C.byref(t)), "hab_server_submit")
+        B.check(self.lib.hab_server_submit_ex(self.h, C.byref(v), int(timeout_us), C.byref(t)),
+                "hab_server_submit_ex")
         self._keep[t.value] = (rgb, depth, tri, semantic)
         return t.value
 
@@ -481,6 +482,16 @@ class Server:
     def _stats(rs):
         return {"submit_ns": rs.submit_ns, "launch_ns": rs.launch_ns, "done_ns": rs.done_ns,
                 "batch_size": rs.batch_size, "batch_id": rs.batch_id}
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was still queued and is now cancelled (its
+        poll/wait then raise with HAB_ERR_CANCELLED); False if it was
+        already launched (it completes)."""
+        s = self.lib.hab_server_cancel(self.h, C.c_uint64(ticket))
+        if s == B.HAB_ERR_NOT_READY:
+            return False
+        B.check(s, "hab_server_cancel")
+        return True
 
     def poll(self, ticket: int):
         rs = B.RequestStats()
@@ -501,7 +512,7 @@ class Server:
     def stats(self):
         st = B.ServerStats()
         B.check(self.lib.hab_server_stats_get(self.h, C.byref(st)), "hab_server_stats_get")
-        return {k: getattr(st, k) for k, _ in B.ServerStats._fields_}
+        return {k: getattr(st, k) for k, _ in B.ServerStats._fields_ if k != "pad"}
 
     def close(self):
         if self.h:

@@ -84,6 +84,8 @@ def test_admission_under_tight_budget(env):
     st = srv.stats()
     assert st["completed"] == 60
     assert 0 < st["peak_inflight_bytes"] <= budget
+    # the budget is the server's whole device scratch, not only a count
+    assert st["scratch_bytes"] == budget
     big = ctx.sensor(4096, 4096, 90.0, 1.0)       # near 1 m keeps the pose in range
     out = ctx.alloc(ctx.sensor(4096, 4096, 90.0, 1.0, P.OUT_DEPTH), 1)
     with pytest.raises(P.HabError) as e:
@@ -92,6 +94,47 @@ def test_admission_under_tight_budget(env):
     assert st["rejected"] == 0 and srv.stats()["rejected"] == 1
     srv.close()
     check_against_alone(ctx, reqs)
+
+
+def test_cancel_and_timeout(env):
+    """With one stream and one request per batch a burst queues up:
+    cancelling queued requests makes their tickets report
+    HAB_ERR_CANCELLED, a request already launched cannot be cancelled and
+    completes, requests with a 1 us deadline behind the backlog time out;
+    everything that completes equals the view rendered alone."""
+    import paper_1904_01201_amd as P
+    ctx, scenes, poses, sensors = env
+    note("server: cancel and timeout")
+    reqs = make_requests(ctx, scenes, poses, [sensors[0]], 60, seed=3)
+    srv = P.Server(ctx, num_streams=1, max_batch=1)
+    tickets = [srv.submit(s, sn, p, o.get("rgb"), o.get("depth"), o.get("tri")) for s, sn, p, o in reqs[:40]]
+    cancelled = [t for t in tickets[10::3] if srv.cancel(t)]
+    assert len(cancelled) >= 5, len(cancelled)
+    timed = [srv.submit(s, sn, p, o.get("rgb"), o.get("depth"), o.get("tri"), timeout_us=1)
+             for s, sn, p, o in reqs[40:]]
+    done, outcome = [], {}
+    for k, t in enumerate(tickets + timed):
+        try:
+            srv.wait(t)
+            outcome[t] = P.HAB_OK
+            done.append(reqs[k])
+        except P.HabError as e:
+            outcome[t] = e.status
+    for t in cancelled:
+        assert outcome[t] == P.HAB_ERR_CANCELLED, t
+    for t in tickets:
+        if t not in cancelled:
+            assert outcome[t] == P.HAB_OK, t
+    expired = [t for t in timed if outcome[t] == P.HAB_ERR_TIMEOUT]
+    assert len(expired) >= 10 and all(outcome[t] in (P.HAB_OK, P.HAB_ERR_TIMEOUT) for t in timed)
+    with pytest.raises(P.HabError) as e:   # collected: unknown now
+        srv.cancel(tickets[0])
+    assert e.value.status == P.HAB_ERR_INVALID_ARG
+    st = srv.stats()
+    assert st["cancelled"] == len(cancelled) and st["expired"] == len(expired)
+    assert st["completed"] == len(done)
+    srv.close()
+    check_against_alone(ctx, done)
 
 
 def test_ticket_semantics(env):
