@@ -3,10 +3,13 @@
 // One launch sequence renders a batch of views (any mix of scenes,
 // resolutions and output sets):
 //   k_reset      zero the per-view, per-tile and work-queue counters
-//   k_setup      per (scene group, triangle): fetch the triangle once, then
-//                for every view of the group transform, clip, snap, orient
-//                and cull; survivors (key, pixel bbox) are appended to the
-//                view's list with wave-level prefix-sum compaction
+//   k_cull       per (view, 64-triangle cluster): conservative frustum test
+//                of the cluster's box; the visible clusters are listed
+//   k_setup      per (view, run of visible clusters): fetch each triangle,
+//                transform, clip, snap, orient and cull it; survivors (key,
+//                pixel bbox) are appended to the view's list with
+//                wave-level prefix-sum compaction (the views of a scene are
+//                consecutive, so its triangles are re-read from L2/MALL)
 //   k_bin<count> per chunk of survivors: LDS histogram of the screen tiles
 //                their boxes touch, one global add per touched tile
 //   k_bin_scan   per view: exclusive scans of the tile counts (list offsets;
