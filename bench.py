@@ -195,12 +195,37 @@ def actuation_leg(ctx, w, a, hs):
            "obstacles": f"mesh cross-sections at {list(NAV_HEIGHTS)} m (hab_nav_from_scene)",
            "nav_from_scene_s": round(t_nav, 4),
            "steps": steps, "agent_steps_per_s": round(n * steps / el), "ms_per_step": round(1e3 * el / steps, 4),
-           "path": "hab_actuate (fp64 collide-and-slide over a uniform 0.5 m grid of obstacle segments)",
+           "path": "hab_actuate (fp64 collide-and-slide over a uniform grid of obstacle segments, cells 0.1-0.5 m)",
            "free_space_queries_per_s": round(len(navs) * nq * qsteps / el_q),
            "free_space_query": f"hab_nav_free, {nq} random points per scene, radius 0.1 m, "
                                f"{free_frac:.2f} free"}
     log(f"actuation: {out['agent_steps_per_s']:.3g} agent steps/s ({out['ms_per_step']} ms per "
         f"{n}-agent step); free space: {out['free_space_queries_per_s']:.3g} queries/s")
+    return out
+
+
+def serving_leg(ctx, w, hs):
+    """The serving form on the bench workload: one 256x256 RGB+D agent per
+    environment (64) over the 4 resident scenes, each walking its own path;
+    closed-loop saturation for 0.5 s, then Poisson arrivals at 70% of it for
+    1 s (p50/p99 from arrival to completion)."""
+    import paper_1904_01201_amd as P
+    from paper_1904_01201_amd import loadgen
+    sensor = ctx.sensor(256, 256)
+    agents = loadgen.Agents(ctx, hs, w.env_scene, [sensor] * w.num_envs, w.poses)
+    srv = P.Server(ctx, num_streams=3, max_batch=256)
+    sat, lat_sat = loadgen.saturate(srv, agents, seconds=0.5)
+    thr, lat, e2e, bs = loadgen.open_loop(srv, agents, rate=0.7 * sat, seconds=1.0, seed=7)
+    st = srv.stats()
+    srv.close()
+    pct = lambda x, q: round(float(np.percentile(x, q)), 3) if x.size else None
+    out = {"agents": w.num_envs, "saturation_rps": round(sat, 1), "offered_rps": round(0.7 * sat, 1),
+           "throughput_rps": round(thr, 1), "p50_ms": pct(e2e, 50), "p99_ms": pct(e2e, 99),
+           "server_p50_ms": pct(lat, 50), "server_p99_ms": pct(lat, 99),
+           "mean_batch": round(float(bs.mean()), 1) if bs.size else None, "requests": int(lat.size),
+           "scratch_bytes": int(st["scratch_bytes"]), "streams": 3,
+           "latency": "p50/p99 arrival -> completion at 70% of closed-loop saturation; server_* submit -> completion"}
+    log(f"serving: saturation {sat:.0f} requests/s, at 70%: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms")
     return out
 
 
@@ -522,6 +547,7 @@ def main():
     # ---------------------------------------------------- the other workloads
     others = {} if a.no_other_workloads else other_workloads(ctx, a)
     actuation = actuation_leg(ctx, w, a, hs)
+    serving = serving_leg(ctx, w, hs)
 
     # ---------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -613,6 +639,7 @@ def main():
         "cpu_baseline": cpu,
         "other_workloads": others,
         "actuation": actuation,
+        "serving": serving,
         "paper_context": {"rgbd_256_fps_1proc": 1042, "rgbd_256_fps_5proc": 1774,
                           "hardware": "Titan Xp + Xeon E5-2690 v4, OpenGL, Matterport3D scene"},
     }

@@ -4,8 +4,9 @@
 // plane, in fp64.  The definition (contact rule, skin, passes, tie order)
 // is stated with hab_actuate in hab.h.
 //
-// Layout: each obstacle set carries a uniform grid built at upload (0.5 m
-// cells; a cell lists every segment whose bounding box overlaps it).  A
+// Layout: each obstacle set carries a uniform grid built at upload (cells
+// of 0.1-0.5 m sized to the segments; a cell lists every segment whose
+// bounding box overlaps it).  A
 // group of G lanes moves one agent (G = 64 for small batches, where one
 // lane per agent would leave the chip idle and expose the dependent
 // cell -> list -> segment loads; fewer for large ones): per pass each lane
@@ -33,7 +34,8 @@
 
 namespace {
 
-constexpr double kNavCell = 0.5;       // grid cell edge, metres
+constexpr double kNavCellMax = 0.5;    // grid cell edge, metres: at most
+constexpr double kNavCellMin = 0.1;    //   and at least (see nav_build)
 constexpr uint32_t kNavMaxDim = 1024;  // cells per axis (the cell grows beyond)
 
 // What the kernel needs of one obstacle set.
@@ -449,8 +451,11 @@ namespace habmi {
 static hab_status nav_build(hab_context *ctx, const float *segments, uint32_t num_segments, hab_nav **out)
 {
     {
-        // the grid: cells of kNavCell (larger when the extent needs more
-        // than kNavMaxDim cells per axis) over the segments' bounding box
+        // the grid over the segments' bounding box: cells of four times the
+        // mean segment length within [kNavCellMin, kNavCellMax] (a few
+        // segments per occupied cell whether the obstacles are whole walls
+        // or a tessellated mesh's short cross-section pieces), larger when
+        // the extent needs more than kNavMaxDim cells per axis
         NavDesc d{};
         std::vector<uint32_t> start, items;
         if (num_segments) {
@@ -461,7 +466,12 @@ static hab_status nav_build(hab_context *ctx, const float *segments, uint32_t nu
                         lo[a] = std::min(lo[a], (double)segments[4ull * j + 2 * e + a]);
                         hi[a] = std::max(hi[a], (double)segments[4ull * j + 2 * e + a]);
                     }
-            double h = kNavCell;
+            double len = 0.0;
+            for (uint32_t j = 0; j < num_segments; ++j) {
+                const float *q = segments + 4ull * j;
+                len += std::hypot((double)q[2] - q[0], (double)q[3] - q[1]);
+            }
+            double h = std::min(kNavCellMax, std::max(kNavCellMin, 4.0 * len / num_segments));
             const double ext = std::max(hi[0] - lo[0], hi[1] - lo[1]);
             if (ext / h + 1.0 > kNavMaxDim) h = ext / (kNavMaxDim - 1);
             d.gx = (uint32_t)((hi[0] - lo[0]) / h) + 1u;

@@ -16,9 +16,10 @@ constexpr uint32_t kMaxSegments = 1u << 14;
 struct RasterLaunch {
     int ts;                    // 8, 16 or 32
     const uint32_t *lview;     // [nl] view index (resolve: block -> view)
-    const uint32_t *lpre;      // [nl] first block of each view (prefix of tile counts)
+    const uint32_t *bpre;      // [nl] first resolve band of each view (32 x 2 pixels each)
     uint32_t nl;
-    uint32_t blocks;           // total tiles (resolve grid)
+    uint32_t blocks;           // total tiles
+    uint32_t bands;            // total resolve bands (resolve grid)
     uint32_t grid;             // persistent raster blocks
     uint64_t item_cap;         // work items the scratch below can hold
     uint2 *items;              // [item_cap] (view, tile | segment << 18)

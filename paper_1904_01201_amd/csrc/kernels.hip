@@ -25,8 +25,10 @@
 //                lane owns one pixel and keeps the nearest candidate (largest
 //                1/w, smaller key on ties) in registers: an atomic-free
 //                z-test; the segment's per-pixel winner goes to scratch
-//   k_resolve<TS> per tile: merge the segments' winners with the same rule,
-//                rebuild the winner, write colour, planar depth and index.
+//   k_resolve<TS> per band of 32 x 2 pixels (one wave): merge the segments'
+//                winners with the same rule, rebuild the winner, write
+//                colour (through LDS, as words), planar depth and index:
+//                whole 32-byte sectors.
 // Coverage and visibility are decided by exact integer edge functions and
 // one fixed sequence of fp32 operations (the key), so outputs do not depend
 // on batching, tile size, capacity, segmenting or scheduling order.
@@ -1302,72 +1304,106 @@ __device__ __forceinline__ float depth_noise_normal(uint64_t seed, uint64_t pixe
     return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 
-// Per tile: merge the segments' winners (largest 1/w, smaller key on a
-// tie: the same order-free rule), then shade and write the outputs.
+// Resolve bands: 32 x 2 pixels of one view per wave (one lane per pixel,
+// four 8-pixel tiles side by side).  Each lane merges its pixel's segment
+// winners (largest 1/w, smaller key on a tie: the same order-free rule) and
+// shades it.  A band row is 96 bytes of RGB at a multiple of 96 (three
+// whole 32-byte sectors) and 128 bytes of depth, index or instance (one
+// whole line): the RGB bytes go through LDS so that the wave stores them as
+// words, and every sector the band writes is written once and whole.
+constexpr int kBandW = 32, kBandH = 2;
+constexpr int kBandThreads = kBandW * kBandH;   // one wave
+
 template <int TS>
-__global__ __launch_bounds__(TS *TS) void k_resolve(const DView *__restrict__ views,
-                                                    const uint32_t *__restrict__ lview,
-                                                    const uint32_t *__restrict__ lpre, uint32_t nl,
-                                                    const uint32_t *__restrict__ tile_count,
-                                                    const uint32_t *__restrict__ tile_off,
-                                                    const uint32_t *__restrict__ tile_item,
-                                                    const uint2 *__restrict__ partial,
-                                                    uint32_t *__restrict__ err)
+__global__ __launch_bounds__(kBandThreads) void k_resolve(const DView *__restrict__ views,
+                                                          const uint32_t *__restrict__ lview,
+                                                          const uint32_t *__restrict__ bpre, uint32_t nl,
+                                                          const uint32_t *__restrict__ tile_count,
+                                                          const uint32_t *__restrict__ tile_off,
+                                                          const uint32_t *__restrict__ tile_item,
+                                                          const uint2 *__restrict__ partial,
+                                                          uint32_t *__restrict__ err)
 {
     constexpr int NT = TS * TS;
     constexpr int NS = TS / 8;
+    __shared__ __align__(16) uint8_t s_rgb[kBandH * kBandW * 3];
     uint32_t lo = 0, hi = nl - 1;
     const uint32_t blk = blockIdx.x;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
-        if (lpre[mid] <= blk) lo = mid;
+        if (bpre[mid] <= blk) lo = mid;
         else hi = mid - 1;
     }
     const uint32_t vi = uniform(lview[uniform(lo)]);
     const DView &v = views[vi];
-    const uint32_t tile = blk - lpre[lo];
-    const int tx = (int)(tile % v.tiles_x), ty = (int)(tile / v.tiles_x);
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    const int pi = tx * TS + (int)(wave % NS) * 8 + (int)(lane & 7u);
-    const int pj = ty * TS + (int)(wave / NS) * 8 + (int)(lane >> 3);
-    if (pi >= (int)v.W || pj >= (int)v.H) return;
-    const uint32_t tglob = v.tile_base + tile;
-    const uint32_t ns = tile_segments(tile_count[tglob], tile_off[tglob], v.ts_log2);
-    const uint32_t first = tile_item[tglob];
-    float best_rho = 0.0f;
-    uint32_t best_key = kNone;
-    for (uint32_t s = 0; s < ns; ++s) {
-        const uint2 pr = partial[(size_t)(first + s) * NT + tid];
-        const float rho = __uint_as_float(pr.x);
-        if (pr.y != kNone && (rho > best_rho || (rho == best_rho && pr.y < best_key))) {
-            best_rho = rho;
-            best_key = pr.y;
-        }
-    }
+    const uint32_t W = v.W, H = v.H;
+    const uint32_t nbx = (W + kBandW - 1) / kBandW;
+    const uint32_t band = blk - bpre[lo];
+    const uint32_t x0 = (band % nbx) * kBandW, y0 = (band / nbx) * kBandH;
+    const uint32_t lane = lane_id();
+    const uint32_t cx = lane % kBandW, cy = lane / kBandW;   // position in the band
+    const int pi = (int)(x0 + cx), pj = (int)(y0 + cy);
+    const bool in = pi < (int)W && pj < (int)H;
     uint32_t rgb[3] = {0, 0, 0};
-    float depth = 0.0f;
-    if (best_key != kNone) {
-        // the depth is the reciprocal of the winning key's 1/w (the value a
-        // rebuild of the triangle would compute again); colour needs the
-        // rebuild
-        depth = 1.0f / best_rho;
-        if (v.rgb && !(v.tex ? resolve_tex(v, best_key, pi, pj, rgb) : resolve(v, best_key, pi, pj, rgb)))
-            atomicOr(err, kErrResolve);
+    if (in) {
+        const uint32_t tile = (uint32_t)(pj / TS) * v.tiles_x + (uint32_t)(pi / TS);
+        const uint32_t sub = (uint32_t)(((pj % TS) / 8) * NS + (pi % TS) / 8);
+        const uint32_t tglob = v.tile_base + tile;
+        const uint32_t ns = tile_segments(tile_count[tglob], tile_off[tglob], v.ts_log2);
+        const uint32_t first = tile_item[tglob];
+        const uint32_t slot = sub * 64u + (uint32_t)((pj % 8) * 8 + (pi % 8));
+        float best_rho = 0.0f;
+        uint32_t best_key = kNone;
+        for (uint32_t s = 0; s < ns; ++s) {
+            const uint2 pr = partial[(size_t)(first + s) * NT + slot];
+            const float rho = __uint_as_float(pr.x);
+            if (pr.y != kNone && (rho > best_rho || (rho == best_rho && pr.y < best_key))) {
+                best_rho = rho;
+                best_key = pr.y;
+            }
+        }
+        float depth = 0.0f;
+        if (best_key != kNone) {
+            // the depth is the reciprocal of the winning key's 1/w (the value
+            // a rebuild of the triangle would compute again); colour needs
+            // the rebuild
+            depth = 1.0f / best_rho;
+            if (v.rgb && !(v.tex ? resolve_tex(v, best_key, pi, pj, rgb) : resolve(v, best_key, pi, pj, rgb)))
+                atomicOr(err, kErrResolve);
+        }
+        const size_t p = (size_t)pj * W + (size_t)pi;
+        if (v.noise_sigma > 0.0f && best_key != kNone) {
+            const float rp = best_rho + v.noise_sigma * depth_noise_normal(v.noise_seed, (uint64_t)p);
+            depth = rp > 0.0f ? 1.0f / rp : 0.0f;
+        }
+        if (v.depth) gmem_out(v.depth)[p] = depth;
+        if (v.tri) gmem_out(v.tri)[p] = best_key == kNone ? kNone : (best_key >> 1);
+        if (v.sem) gmem_out(v.sem)[p] = best_key == kNone ? kNone : gmem(v.inst)[best_key >> 1];
     }
-    const size_t p = (size_t)pj * v.W + (size_t)pi;
-    if (v.noise_sigma > 0.0f && best_key != kNone) {
-        const float rp = best_rho + v.noise_sigma * depth_noise_normal(v.noise_seed, (uint64_t)p);
-        depth = rp > 0.0f ? 1.0f / rp : 0.0f;
+    if (!v.rgb) return;
+    auto *o = gmem_out(v.rgb);
+    const uint32_t wpx = min((uint32_t)kBandW, W - x0), rows = min((uint32_t)kBandH, H - y0);
+    if ((W % 4u) == 0 && (reinterpret_cast<uintptr_t>(v.rgb) % 4u) == 0) {
+        // rows of 3 wpx bytes start on a word (the image does, W and x0 are
+        // multiples of 4): stage the band's bytes, store words
+        constexpr uint32_t kRowWords = kBandW * 3u / 4u;   // 24
+        s_rgb[3 * lane] = (uint8_t)rgb[0];
+        s_rgb[3 * lane + 1] = (uint8_t)rgb[1];
+        s_rgb[3 * lane + 2] = (uint8_t)rgb[2];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t r = lane / kRowWords, d = lane % kRowWords;
+        if (lane < kBandH * kRowWords && r < rows && d < wpx * 3u / 4u) {
+            auto *dst = reinterpret_cast<__attribute__((address_space(1))) uint32_t *>(
+                o + ((size_t)(y0 + r) * W + x0) * 3u);
+            dst[d] = reinterpret_cast<const uint32_t *>(s_rgb)[lane];
+        }
+    } else if (in) {
+        auto *q = o + 3 * ((size_t)pj * W + (size_t)pi);
+        q[0] = (uint8_t)rgb[0];
+        q[1] = (uint8_t)rgb[1];
+        q[2] = (uint8_t)rgb[2];
     }
-    if (v.rgb) {
-        auto *o = gmem_out(v.rgb) + 3 * p;
-        o[0] = (uint8_t)rgb[0];
-        o[1] = (uint8_t)rgb[1];
-        o[2] = (uint8_t)rgb[2];
-    }
-    if (v.depth) gmem_out(v.depth)[p] = depth;
-    if (v.tri) gmem_out(v.tri)[p] = best_key == kNone ? kNone : (best_key >> 1);
-    if (v.sem) gmem_out(v.sem)[p] = best_key == kNone ? kNone : gmem(v.inst)[best_key >> 1];
 }
 
 // ------------------------------------------------------------ host side
@@ -1388,7 +1424,7 @@ static void launch_raster(const LaunchPlan &L, const RasterLaunch &R, hipStream_
 template <int TS>
 static void launch_resolve(const LaunchPlan &L, const RasterLaunch &R, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resolve<TS>, dim3(R.blocks), dim3(TS * TS), 0, s, L.views, R.lview, R.lpre,
+    hipLaunchKernelGGL(k_resolve<TS>, dim3(R.bands), dim3(kBandThreads), 0, s, L.views, R.lview, R.bpre,
                        R.nl, L.tile_count, L.tile_off, L.tile_item, R.partial, L.err);
 }
 

@@ -390,10 +390,11 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     for (int c = 0; c < 3; ++c) {
         stable_sort_views(lview[c].begin(), lview[c].end(),
                           [&](uint32_t a, uint32_t b) { return dv[a].T > dv[b].T; });
+        // lpre: each view's first resolve band (32 x 2 pixels)
         uint32_t pre = 0;
         for (uint32_t k : lview[c]) {
             lpre[c].push_back(pre);
-            pre += dv[k].tiles_x * dv[k].tiles_y;
+            pre += cdiv(dv[k].W, 32u) * cdiv(dv[k].H, 2u);
         }
     }
     if (tile_total >= kIndexLimit || surv_total >= kIndexLimit || bin_total >= kIndexLimit ||
@@ -485,7 +486,9 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         R.ts = c == 0 ? 8 : c == 1 ? 16 : 32;
         R.nl = (uint32_t)lview[c].size();
         const DView &last = dv[lview[c].back()];
-        R.blocks = lpre[c].back() + last.tiles_x * last.tiles_y;
+        R.blocks = 0;
+        for (uint32_t k : lview[c]) R.blocks += dv[k].tiles_x * dv[k].tiles_y;
+        R.bands = lpre[c].back() + cdiv(last.W, 32u) * cdiv(last.H, 2u);
         R.item_cap = item_cap[c];
         R.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(item_cap[c], (uint64_t)cus * kBlocksPerCu[c]));
     }
@@ -513,7 +516,7 @@ void bind_plan(Plan &plan, void *arena, uint32_t *err)
         RasterLaunch &R = L.raster[k];
         const int c = R.ts == 8 ? 0 : R.ts == 16 ? 1 : 2;
         R.lview = reinterpret_cast<const uint32_t *>(b + plan.off_lview[c]);
-        R.lpre = reinterpret_cast<const uint32_t *>(b + plan.off_lpre[c]);
+        R.bpre = reinterpret_cast<const uint32_t *>(b + plan.off_lpre[c]);
         R.items = reinterpret_cast<uint2 *>(b + plan.off_items[c]);
         R.partial = reinterpret_cast<uint2 *>(b + plan.off_partial[c]);
     }
