@@ -366,15 +366,35 @@ def main():
         phases[k] = v      # the dominant kernel's time is the one taken in the timed steps
     fps_batch = E * a.steps / t_batch
     log(f"batched eager: {fps_batch:.0f} frames/s ({1e3 * t_batch / a.steps:.3f} ms/step)")
-    log("phases (ms/step): " + ", ".join(f"{k}={v['ms'] / max(v['launches'], 1):.4f}"
+    log("phases (ms/step): " + ", ".join(f"{k}={v['ms'] / a.steps:.4f} ({v['launches'] / a.steps:g} launches)"
                                          for k, v in phases.items()))
 
     if a.profile_only:
         print(json.dumps({"profile_only": True, "batched_fps": round(fps_batch, 1),
-                          "phase_ms_per_step": {k: v["ms"] / max(v["launches"], 1)
-                                                for k, v in phases.items()}}), flush=True)
+                          "phase_ms_per_step": {k: v["ms"] / a.steps for k, v in phases.items()},
+                          "phase_ms_per_launch": {k: v["ms"] / max(v["launches"], 1)
+                                                  for k, v in phases.items()}}), flush=True)
         ctx.close()
         return
+
+    # ---------------------------------------------------- one launch sequence
+    # The same steps with the batch kept in one launch sequence (no halves
+    # side by side): its rate, and the raster's duration when no other
+    # kernel shares the GPU with it (reported beside the roofline).
+    ctx.profile_phases(RASTER_PHASES)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        set_poses(s)
+        ctx.render_batch(None, views=views, tile_size=a.tile_size, one_sequence=True)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    ctx.profile(False)
+    one_phases = ctx.profile_read()
+    ctx.profile_phases(None)
+    fps_one = E * a.steps / t_one
+    log(f"batched eager, one launch sequence: {fps_one:.0f} frames/s")
 
     # ---------------------------------------------------- batched (graph)
     st = ctx.stepper(items0, tile_size=a.tile_size)
@@ -507,17 +527,24 @@ def main():
     assert ctx.get_error() == 0
 
     # ---------------------------------------------------- roofline
+    # A step of 32 views or more is two launch sequences (halves of the
+    # batch) that run side by side: per-launch times are each half's own
+    # kernel durations, and the work of one launch is half a step's.
     per_launch = {k: v["ms"] / max(v["launches"], 1) for k, v in phases.items()}
+    per_step = {k: v["ms"] / a.steps for k, v in phases.items()}
+    lps = {k: v["launches"] / a.steps for k, v in phases.items()}
     raster = [k for k in phases if k.startswith("raster")]
     if raster:
-        # every raster launch of a step (one per tile size in use) together
+        # every raster launch of a launch sequence (one per tile size in use) together
         per_launch["raster"] = sum(phases[k]["ms"] for k in raster) / max(phases[raster[0]]["launches"], 1)
+        per_step["raster"] = sum(phases[k]["ms"] for k in raster) / a.steps
+        lps["raster"] = lps[raster[0]]
     dom = max(((k, v) for k, v in per_launch.items() if k not in raster), key=lambda kv: kv[1])[0]
     geom_bytes = sum(15 * s.num_vertices + 12 * s.num_triangles for s in w.scenes)
     out_bytes = E * 256 * 256 * 7
     step_bytes = out_bytes + geom_bytes + 48 * E
     if dom == "raster":
-        ops = OPS_PER_TEST * bbox_tests + OPS_PER_COVERED * covered
+        ops = (OPS_PER_TEST * bbox_tests + OPS_PER_COVERED * covered) / lps[dom]
         ach = ops / (per_launch[dom] * 1e-3) / 1e12
         kern = "+".join(f"k_raster<{k[6:]}>" for k in raster)
         tr = measured_traffic(kern)
@@ -526,10 +553,19 @@ def main():
                 "traffic": round(tr["bytes_per_launch"]) if tr else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": round(per_launch[dom], 5),
-                "work_per_launch": {"bbox_tests": bbox_tests, "covered": covered,
-                                    "ops": ops}}
+                "launches_per_step": lps[dom],
+                "work_per_launch": {"bbox_tests": round(bbox_tests / lps[dom]),
+                                    "covered": round(covered / lps[dom]), "ops": round(ops)}}
+        ms_one = sum(one_phases[k]["ms"] for k in raster if k in one_phases) / a.steps
+        ops_one = OPS_PER_TEST * bbox_tests + OPS_PER_COVERED * covered
+        roof_one = {"kernel": kern, "what": "the same steps in one launch sequence: one raster "
+                    "launch per step with no other kernel beside it (not the timed steps)",
+                    "achieved": round(ops_one / (ms_one * 1e-3) / 1e12, 4), "unit": "TOP/s",
+                    "frac": round(ops_one / (ms_one * 1e-3) / 1e12 / ALU_PEAK_TOPS, 5),
+                    "avg_launch_ms": round(ms_one, 5), "fps": round(fps_one, 1)}
     else:
-        byts = geom_bytes + E * 16 * 8 if dom == "setup" else step_bytes
+        roof_one = None
+        byts = (geom_bytes + E * 16 * 8 if dom == "setup" else step_bytes) / lps[dom]
         ach = byts / (per_launch[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
@@ -632,9 +668,12 @@ def main():
         "batched_over_per_view": round(fps_batch / fps_pv, 2),
         "p50_step_ms": round(p50, 4),
         "p99_step_ms": round(p99, 4),
-        "phase_ms_per_step": {k: round(v, 5) for k, v in per_launch.items()},
+        "phase_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
+        "phase_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
+        "launches_per_step": lps.get("raster", 1),
         "work": {"survivors": survivors, "bbox_tests": bbox_tests, "covered": covered},
         "roofline": roof,
+        "roofline_one_sequence": roof_one,
         "hbm_roofline": hbm,
         "cpu_baseline": cpu,
         "other_workloads": others,

@@ -169,12 +169,23 @@ typedef struct {
 /* Launch options.  Zero-initialised = defaults.  tile_size in {0, 8, 16,
  * 32} (0: autotuned/default); bin_factor: per-view bin capacity as a
  * multiple of the triangle count (0: default); tile_cap: entries a tile
- * list may hold before the tile takes the overflow path (0: unlimited).
- * None of these changes any output bit. */
+ * list may hold before the tile takes the overflow path (0: unlimited);
+ * flags: HAB_RENDER_* bits (others: HAB_ERR_INVALID_ARG).  None of these
+ * changes any output bit.
+ *
+ * A batch of 32 or more views is rendered as two launch sequences over
+ * interleaved halves (views 0, 2, 4, ... and 1, 3, 5, ...): one on the
+ * caller's stream, one on a second stream of the context that waits for the
+ * caller's stream first, and the caller's stream then waits for it, so the
+ * call orders like one launch on the caller's stream.  The halves' kernels
+ * overlap on the GPU.  HAB_RENDER_ONE_SEQUENCE keeps the batch in one
+ * launch sequence. */
+#define HAB_RENDER_ONE_SEQUENCE 1u
 typedef struct {
     uint32_t tile_size;
     float bin_factor;
     uint32_t tile_cap;
+    uint32_t flags;
     hab_view_stats *stats; /* host array [N] or NULL; written after completion */
 } hab_render_opts;
 

@@ -29,6 +29,7 @@ HAB_ERR_CANCELLED = 7
 HAB_ERR_TIMEOUT = 8
 HAB_NO_HIT = 0xFFFFFFFF
 OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC = 1, 2, 4, 8
+RENDER_ONE_SEQUENCE = 1
 
 EXPORTED = [
     "hab_init", "hab_shutdown", "hab_status_string", "hab_get_error",
@@ -75,7 +76,7 @@ class ViewStats(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("tile_size", C.c_uint32), ("bin_factor", C.c_float), ("tile_cap", C.c_uint32),
-                ("stats", C.POINTER(ViewStats))]
+                ("flags", C.c_uint32), ("stats", C.POINTER(ViewStats))]
 
 
 class View(C.Structure):

@@ -43,6 +43,7 @@ hab_status hab_init(int device, hab_context **out)
         hab_context *ctx = new hab_context();
         ctx->device = device;
         ctx->ws.device = device;
+        ctx->ws2.device = device;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
             ctx->cu_count = prop.multiProcessorCount;
@@ -94,6 +95,9 @@ hab_status hab_shutdown(hab_context *ctx)
         release_navs(ctx);
         for (auto &ps : ctx->prof_sets)
             for (auto &e : ps.ev) (void)hipEventDestroy(e);
+        if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+        if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+        if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
         if (ctx->err) dev_free(ctx->err);
         delete ctx;
         return HAB_OK;
@@ -303,7 +307,7 @@ static hab_status render_common(hab_context *ctx, const hab_scene *scene, const 
     if (st != HAB_OK) return st;
     if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
         return HAB_ERR_INVALID_ARG;
-    if (opts && opts->bin_factor < 0.0f) return HAB_ERR_INVALID_ARG;
+    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_ONE_SEQUENCE))) return HAB_ERR_INVALID_ARG;
     return guarded([&]() -> hab_status {
         std::vector<ViewReq> req(n);
         const size_t px = (size_t)sensor->width * sensor->height;
@@ -324,10 +328,11 @@ static hab_status render_common(hab_context *ctx, const hab_scene *scene, const 
             o.tile_size = opts->tile_size;
             o.bin_factor = opts->bin_factor;
             o.tile_cap = opts->tile_cap;
+            o.one_sequence = (opts->flags & HAB_RENDER_ONE_SEQUENCE) != 0;
         }
         DeviceGuard g(ctx->device);
         if (!g.ok) return HAB_ERR_DEVICE;
-        return render_all(ctx, ctx->ws, req.data(), n, o, stream, opts ? opts->stats : nullptr);
+        return render_split(ctx, req.data(), n, o, stream, opts ? opts->stats : nullptr);
     });
 }
 
@@ -355,7 +360,7 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t n,
     if (n == 0) return HAB_OK;
     if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
         return HAB_ERR_INVALID_ARG;
-    if (opts && opts->bin_factor < 0.0f) return HAB_ERR_INVALID_ARG;
+    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_ONE_SEQUENCE))) return HAB_ERR_INVALID_ARG;
     return guarded([&]() -> hab_status {
         std::vector<ViewReq> req(n);
         for (uint32_t k = 0; k < n; ++k) {
@@ -367,10 +372,11 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t n,
             o.tile_size = opts->tile_size;
             o.bin_factor = opts->bin_factor;
             o.tile_cap = opts->tile_cap;
+            o.one_sequence = (opts->flags & HAB_RENDER_ONE_SEQUENCE) != 0;
         }
         DeviceGuard g(ctx->device);
         if (!g.ok) return HAB_ERR_DEVICE;
-        return render_all(ctx, ctx->ws, req.data(), n, o, stream, opts ? opts->stats : nullptr);
+        return render_split(ctx, req.data(), n, o, stream, opts ? opts->stats : nullptr);
     });
 }
 

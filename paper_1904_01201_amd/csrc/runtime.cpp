@@ -640,4 +640,43 @@ hab_status render_all(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     return HAB_OK;
 }
 
+hab_status ensure_aux(hab_context *ctx)
+{
+    if (!ctx->aux) HAB_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    if (!ctx->fork_ev) HAB_HIP(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    if (!ctx->join_ev) HAB_HIP(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+    return HAB_OK;
+}
+
+hab_status render_split(hab_context *ctx, const ViewReq *v, uint32_t n, const PlanOpts &o, hipStream_t s,
+                        hab_view_stats *stats)
+{
+    if (n < kSplitViews || o.one_sequence) return render_all(ctx, ctx->ws, v, n, o, s, stats);
+    hab_status st = ensure_aux(ctx);
+    if (st != HAB_OK) return st;
+    // views 0, 2, 4, ... and 1, 3, 5, ...: halves of like composition
+    std::vector<ViewReq> half[2];
+    std::vector<hab_view_stats> hs[2];
+    for (int h = 0; h < 2; ++h) {
+        half[h].reserve((n + 1) / 2);
+        if (stats) hs[h].resize((n + 1 - (uint32_t)h) / 2);
+    }
+    for (uint32_t k = 0; k < n; ++k) half[k & 1u].push_back(v[k]);
+    HAB_HIP(hipEventRecord(ctx->fork_ev, s));
+    HAB_HIP(hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+    st = render_all(ctx, ctx->ws, half[0].data(), (uint32_t)half[0].size(), o, s,
+                    stats ? hs[0].data() : nullptr);
+    if (st == HAB_OK)
+        st = render_all(ctx, ctx->ws2, half[1].data(), (uint32_t)half[1].size(), o, ctx->aux,
+                        stats ? hs[1].data() : nullptr);
+    // the join is enqueued whatever happened, so that s is ordered after
+    // everything the call put on the second stream
+    HAB_HIP(hipEventRecord(ctx->join_ev, ctx->aux));
+    HAB_HIP(hipStreamWaitEvent(s, ctx->join_ev, 0));
+    if (st != HAB_OK) return st;
+    if (stats)
+        for (uint32_t k = 0; k < n; ++k) stats[k] = hs[k & 1u][k >> 1];
+    return HAB_OK;
+}
+
 }  // namespace habmi

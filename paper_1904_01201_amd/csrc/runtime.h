@@ -91,6 +91,7 @@ struct PlanOpts {
     float bin_factor = 0.0f;    // 0: default
     uint32_t tile_cap = 0;      // 0: unlimited
     bool count_work = false;    // accumulate bbox tests / covered fragments
+    bool one_sequence = false;  // never split a batch into two launch sequences
 };
 
 // Sizes of one launch sequence; used for memory admission as well.
@@ -154,6 +155,12 @@ struct Plan {
     uint32_t n = 0;
 };
 
+// Batches of at least this many views render as two interleaved halves,
+// each its own launch sequence, on the caller's stream and a second stream
+// of the context: the halves' kernels overlap, so one half's low-occupancy
+// phases (the setup's tail, binning) run beside the other's raster.
+constexpr uint32_t kSplitViews = 32;
+
 struct Tuned {
     uint32_t key;
     uint32_t ts;
@@ -165,6 +172,12 @@ struct Tuned {
 struct hab_context {
     int device = 0;
     habmi::Workspace ws;
+    // the second half of a split batch: its workspace and stream, and the
+    // events that order it after the caller's stream and back (made on
+    // first use)
+    habmi::Workspace ws2;
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint32_t *err = nullptr;          // device error word
     std::vector<habmi::Scene *> scenes;
     std::vector<habmi::Tuned> tuned;  // autotune table
@@ -234,6 +247,13 @@ void autotune_cache_load(hab_context *ctx);
 // them all.
 hab_status render_all(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_t n,
                       const PlanOpts &o, hipStream_t s, hab_view_stats *stats);
+// render_all on the context's workspace; a batch of kSplitViews or more
+// views as two interleaved halves on s and the context's second stream
+// (joined back into s before returning).
+hab_status render_split(hab_context *ctx, const ViewReq *v, uint32_t n, const PlanOpts &o, hipStream_t s,
+                        hab_view_stats *stats);
+// The second stream and its events (once per context).
+hab_status ensure_aux(hab_context *ctx);
 Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context *ctx);
 hab_status to_view_req(const hab_view &hv, ViewReq &out);
 

@@ -152,6 +152,69 @@ def test_batch_equals_alone(ctx):
     ctx.release(s_apt)
 
 
+def test_split_batch_equals_alone(ctx):
+    """Batches of 32 views or more render as two halves side by side (eager
+    batch, plain entry point, graph stepper): every view's output and work
+    counters equal those of the view rendered alone, and so do the outputs
+    at 31 views and with HAB_RENDER_ONE_SEQUENCE (one launch sequence)."""
+    import torch
+    note("split batch vs alone")
+    room = configs.room_2k_128()
+    apt = make_apartment(seed=78, target_T=20_000)
+    s_room, s_apt = ctx.upload_scene(room.scenes[0]), ctx.upload_scene(apt)
+    sn = ctx.sensor(64, 64)
+    poses_room = room.poses[:20, 0]
+    poses_apt = random_walks(apt, 20, 2, seed=6)[-1]
+    for n in (41, 31):
+        items, alone, alone_stats = [], [], []
+        for k in range(n):
+            scene, pose = ((s_room, poses_room[(k // 2) % 20]) if k % 2 == 0
+                           else (s_apt, poses_apt[(k // 2) % 20]))
+            o = ctx.alloc(sn, 1, tri=True)
+            items.append((scene, sn, pose, o["rgb"], o["depth"], o["tri"]))
+            a = ctx.render(scene, sn, pose, out=ctx.alloc(sn, 1, tri=True), stats=True)
+            alone.append(a)
+            alone_stats.append(a["stats"][0])
+        for one in (False, True):
+            for it in items:
+                for j in (3, 4, 5):
+                    it[j].zero_()
+            stats = ctx.render_batch(items, stats=True, one_sequence=one)
+            torch.cuda.synchronize()
+            for k, (it, a) in enumerate(zip(items, alone)):
+                for j, name in ((3, "rgb"), (4, "depth"), (5, "tri")):
+                    assert torch.equal(it[j], a[name]), (n, one, k, name)
+                assert stats[k] == alone_stats[k], (n, one, k)
+        # the graph stepper over the same views, with host and device poses
+        st = ctx.stepper(items)
+        pz = np.stack([np.asarray(it[2], np.float32).reshape(12) for it in items])
+        for how in ("host", "device"):
+            for it in items:
+                for j in (3, 4, 5):
+                    it[j].zero_()
+            if how == "host":
+                st.step(pz)
+            else:
+                st.step_device(torch.from_numpy(pz).cuda())
+            torch.cuda.synchronize()
+            for k, (it, a) in enumerate(zip(items, alone)):
+                for j, name in ((3, "rgb"), (4, "depth"), (5, "tri")):
+                    assert torch.equal(it[j], a[name]), ("stepper", how, n, k, name)
+        st.close()
+    # the plain entry point: 40 poses of one scene in one call
+    poses = np.concatenate([poses_room, poses_room[::-1]])
+    got = ctx.render(s_room, sn, poses, out=ctx.alloc(sn, 40, tri=True), stats=True)
+    torch.cuda.synchronize()
+    for k in range(40):
+        a = ctx.render(s_room, sn, poses[k], out=ctx.alloc(sn, 1, tri=True), stats=True)
+        torch.cuda.synchronize()
+        for name in ("rgb", "depth", "tri"):
+            assert torch.equal(got[name][k], a[name][0]), ("plain", k, name)
+        assert got["stats"][k] == a["stats"][0], ("plain", k)
+    ctx.release(s_room)
+    ctx.release(s_apt)
+
+
 def test_stepper_graph_replay(ctx):
     """Graph-captured steps: each replay (new poses) equals an eager batch
     render of the same poses; eager work runs between replays."""
@@ -230,5 +293,19 @@ def test_argument_errors(ctx):
     with pytest.raises(P.HabError) as e:
         ctx.upload(pos, None, idx + 7)
     assert e.value.status == P.HAB_ERR_INVALID_ARG
+    # an unknown launch-option flag, on every entry point that takes options
+    import ctypes as C
+    from paper_1904_01201_amd import binding as B
+    good, bad = B.RenderOpts(0, 0.0, 0, 1, None), B.RenderOpts(0, 0.0, 0, 2, None)
+    o = ctx.alloc(s, 1)
+    views = ctx.make_views([(sc, s, pose_at(0, 0, 0), o["rgb"], o["depth"], None)])
+    assert ctx.lib.hab_render_batch(ctx.h, views, 1, C.byref(bad), None) == P.HAB_ERR_INVALID_ARG
+    assert ctx.lib.hab_render_batch(ctx.h, views, 1, C.byref(good), None) == P.HAB_OK
+    pc = B.poses_to_c(np.asarray(pose_at(0, 0, 0), np.float32).reshape(1, 12))
+    assert ctx.lib.hab_render_ex(ctx.h, C.c_void_p(sc.ptr), C.byref(s), pc, 1, o["rgb"].data_ptr(),
+                                 o["depth"].data_ptr(), None, C.byref(bad), None) == P.HAB_ERR_INVALID_ARG
+    h = C.c_void_p()
+    assert ctx.lib.hab_stepper_create(ctx.h, views, 1, C.byref(bad), None, C.byref(h)) == \
+        P.HAB_ERR_INVALID_ARG
     assert ctx.get_error() == 0
     ctx.release(sc)
