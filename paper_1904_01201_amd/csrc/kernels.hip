@@ -21,10 +21,13 @@
 //   k_raster<TS> persistent blocks pull (tile, segment) items from the queue
 //                (an atomic counter used for work distribution only).  The
 //                segment's triangles are staged through LDS (each lane
-//                rebuilds one edge setup relative to the tile), then every
-//                lane owns one pixel and keeps the nearest candidate (largest
-//                1/w, smaller key on ties) in registers: an atomic-free
-//                z-test; the segment's per-pixel winner goes to scratch
+//                rebuilds one edge setup relative to the tile, with the
+//                pixel blocks its box and edges leave), then the wave lists
+//                the (triangle, block) pairs and each step gives every lane
+//                group one pair: the group's lanes test that block's pixels
+//                and keep the nearest candidate (largest 1/w, smaller key on
+//                ties) by an LDS atomic max per pixel; the segment's
+//                per-pixel winner goes to scratch
 //   k_resolve<TS> per band of 32 x 2 pixels (one wave): merge the segments'
 //                winners with the same rule, rebuild the winner, write
 //                colour (through LDS, as words), planar depth and index:
@@ -699,12 +702,11 @@ struct alignas(16) LRec {
     uint32_t nkey;     // ~key: the low word of the z-key
     float rw0, rw1, rw2, invA;
 };
-struct alignas(16) LExt {
+struct alignas(8) LExt {
     int ny0, ny1, ny2; // -dy_k (unpacked records)
     int hi0, hi1, hi2; // slow: high words of C_k
-    int pad0, pad1;
 };
-static_assert(sizeof(LRec) == 48 && sizeof(LExt) == 32, "LDS records");
+static_assert(sizeof(LRec) == 48 && sizeof(LExt) == 24, "LDS records");
 
 // One record as three 16-byte LDS loads, at a byte offset from the array.
 __device__ __forceinline__ LRec lds_rec_at(const char *base, uint32_t off)
@@ -745,7 +747,38 @@ struct Blk {
     static constexpr int W = 1 << WL, H = 1 << HL, NX = TS / W, NY = TS / H;
 };
 template <int TS>
-using QMask = typename std::conditional<TS == 32, unsigned long long, uint32_t>::type;
+using QMask = typename std::conditional<TS == 32, unsigned long long,
+                                        typename std::conditional<TS == 8, uint8_t, uint32_t>::type>::type;
+
+// The bits a raster pair entry carries for block b of a wave's 8 x 8 pixels
+// (bx = b % 2, by = b / 2): the block's offset in the packed (Q, P) pair of
+// 1/256-pixel coordinates (Q in the low half, P in the high half) and in
+// the wave's z-keys (8 bytes per pixel, row-major), both placed so that an
+// OR with the lane's own offsets adds them; the record's offset sits in bits
+// 12..23 and touches neither.
+template <int TS>
+__host__ __device__ constexpr uint32_t pair_bits(int b)
+{
+    using B = Blk<TS>;
+    const uint32_t bx = (uint32_t)(b & 1), by = (uint32_t)(b >> 1);
+    return (by * B::H * 256u) | ((bx * B::W * 256u) << 16) | ((by * B::H * 8u + bx * B::W) * 8u);
+}
+template <int TS>
+__host__ __device__ constexpr uint32_t pair_bits_all()
+{
+    uint32_t m = 0;
+    for (int b = 0; b < 2 * (8 / Blk<TS>::H); ++b) m |= pair_bits<TS>(b);
+    return m;
+}
+// the z-key offsets are below 512 bytes, the (Q, P) offsets at or above
+template <int TS>
+constexpr uint32_t kPairZ = pair_bits_all<TS>() & 0x1FFu;
+template <int TS>
+constexpr uint32_t kPairQP = pair_bits_all<TS>() & ~0x1FFu;
+static_assert(kPairZ<8> == 0x1A0u && kPairQP<8> == 0x04000600u, "pair bits, 8-pixel tiles");
+static_assert(kPairZ<16> == 0x120u && kPairQP<16> == 0x04000400u, "pair bits, larger tiles");
+static_assert(((kPairZ<8> | kPairQP<8>) & 0x00FFF000u) == 0 && ((kPairZ<32> | kPairQP<32>) & 0x00FFF000u) == 0,
+              "record offset bits");
 
 template <int TS>
 __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0, int tj0, LRec &r, LExt &x,
@@ -1041,7 +1074,8 @@ __device__ __forceinline__ bool resolve_tex(const DView &v, uint32_t key, int i,
 
 template <int TS>
 // 6 waves per SIMD: the register budget (80 VGPRs) that lets enough
-// waves hide the LDS and staging latency; a 32-pixel tile's LDS allows 4.
+// waves hide the LDS and staging latency (the LDS of an 8-pixel tile,
+// 7.3 KB, allows 22 blocks per CU); a 32-pixel tile's LDS allows 4.
 __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32 ? 4 : 6))) void k_raster(const DView *__restrict__ views,
                                                    const uint2 *__restrict__ items,
                                                    DQueue *__restrict__ q,
@@ -1065,19 +1099,31 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     __shared__ LRec srec[NT];
     __shared__ LExt sext[NT];
     __shared__ QM sqm[NT];
-    // per wave and block: byte offsets in srec of the chunk's records that
-    // touch the block (zeroed once, so a stale entry is still a record)
-    __shared__ __align__(8) uint32_t slist[NT / 64][NL][64];
+    // lane groups of one block's size; a step gives each group one (record,
+    // block) pair
+    constexpr uint32_t GS = B::W * B::H, NG = 64 / GS;
+    static_assert(NG == NL, "one lane group per block of a wave");
+    // per wave: the chunk's (record, block) pairs, record by record (zeroed
+    // once, so a stale entry is still a pair; padded for the last double
+    // step's read)
+    __shared__ __align__(8) uint32_t slist[NT / 64][NL * 64 + 2 * NG];
+    // per wave: the best z-key of each of its 64 pixels (row-major 8 x 8)
+    __shared__ unsigned long long szb[NT / 64][64];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const unsigned long long lt = lanemask_lt();
-    for (uint32_t i = lane; i < NL * 64; i += 64) (&slist[wave][0][0])[i] = 0;
+    for (uint32_t i = lane; i < NL * 64 + 2 * NG; i += 64) slist[wave][i] = 0;
     const int sx = (int)(wave % NS), sy = (int)(wave / NS);
-    const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
-    const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
-    // (Q, P) as a 16-bit pair for the packed edge records: dot2 gives dx Q - dy P
-    const short2_t QP = __builtin_bit_cast(short2_t, (uint32_t)Q | ((uint32_t)P << 16));
+    // a lane's place in its group's block: (pxl, pyl); the group's block b
+    // (bx = b % 2, by = b / 2 in the wave's 8 x 8 pixels) comes with the
+    // pair.  QPl: (Q, P) of that place in block 0 as a 16-bit pair for the
+    // packed edge records (dot2 gives dx Q - dy P); zl: its byte offset in
+    // the wave's z-keys.
+    const uint32_t pxl = lane % B::W, pyl = (lane % GS) / B::W;
+    const uint32_t QPl = (256u * (uint32_t)(sy * 8 + (int)pyl)) | ((256u * (uint32_t)(sx * 8 + (int)pxl)) << 16);
+    const uint32_t zl = (pyl * 8 + pxl) * 8;
+    unsigned long long *const zw = &szb[wave][0];
     const uint32_t total = q->total[cls];
     bool rerr = false;
 
@@ -1100,8 +1146,6 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
         const DView &v = views[vi];
         const int tx = (int)(tile % v.tiles_x), ty = (int)(tile / v.tiles_x);
         const int ti0 = tx * TS, tj0 = ty * TS;
-        const bool inview = ti0 + sx * 8 + li < (int)v.W && tj0 + sy * 8 + lj < (int)v.H;
-        const unsigned long long inmask = __ballot(inview);
         const bool count = v.count_work != 0;
 
         const uint32_t tglob = v.tile_base + tile;
@@ -1112,11 +1156,14 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
         const uint32_t end = over ? ctr[vi].surv_count : min(begin + S, cnt);
         const uint32_t *list = bins + v.bin_base + (over ? 0u : off);
 
-        // z-key of the best fragment so far: 1/w bits above the complemented
-        // triangle key.  A covered fragment has 1/w > 0 (positive weights,
-        // positive twice-area), so one unsigned max orders by largest 1/w,
-        // then smaller key; 0 means no fragment.
-        unsigned long long best = 0ull;
+        // z-key of the best fragment so far at each pixel of the wave: 1/w
+        // bits above the complemented triangle key.  A covered fragment has
+        // 1/w > 0 (positive weights, positive twice-area), so one unsigned
+        // max orders by largest 1/w, then smaller key; 0 means no fragment.
+        // Any lane group may test any pixel block, so the keys are kept in
+        // LDS and merged by atomic max.
+        zw[lane] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         uint32_t ncov = 0;
 
         for (uint32_t base = begin; base < end; base += NT) {
@@ -1148,20 +1195,33 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             }
             __syncthreads();
             const uint32_t m = min((uint32_t)NT, end - base);
-            // z-test of this lane's pixel against fragment weights w_k where
-            // covered (cov) and the wave's coverage ballot cm
-            auto zkeep = [&](const LRec &R, bool cov, float w0, float w1, float w2) {
+            // z-test of the pixel of pair entry `en` against fragment weights
+            // w_k where covered (cov)
+            auto zkeep = [&](const LRec &R, uint32_t en, uint32_t qp, bool cov, float w0, float w1, float w2) {
                 const float num = (w0 + w1) + w2;
                 const float rho = num * R.invA;
                 const unsigned long long cand =
                     ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
-                if (count) ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
-                best = (cov && cand > best) ? cand : best;
+                if (count) {
+                    // pixels outside the view do not count
+                    const bool inv = ti0 + (int)(qp >> 24) < (int)v.W && tj0 + (int)((qp & 0xFFFFu) >> 8) < (int)v.H;
+                    ncov += (uint32_t)__popcll(__ballot(cov && inv));
+                }
+                if (cov) {
+                    unsigned long long *z = reinterpret_cast<unsigned long long *>(
+                        reinterpret_cast<char *>(zw) + ((en & kPairZ<TS>) | zl));
+                    atomicMax(z, cand);
+                }
             };
-            // one step: every active lane tests its pixel against record R
-            // (index k) of its block under the top-left rule (an edge not
-            // owned needs E > 0)
-            auto visit = [&](const LRec &R, uint32_t k, bool act, auto allpk) {
+            // one step: every active lane tests the pixel its pair entry
+            // names against the pair's record under the top-left rule (an
+            // edge not owned needs E > 0)
+            const char *const rb = reinterpret_cast<const char *>(srec);
+            auto visit = [&](uint32_t en, bool act, auto allpk) {
+                const uint32_t off = ((en >> 12) & 0xFFFu) << 4;
+                const LRec R = lds_rec_at(rb, off);
+                const uint32_t qp = (en & kPairQP<TS>) | QPl;
+                const short2_t QP = __builtin_bit_cast(short2_t, qp);
                 const uint32_t fl = R.flags;
                 const int n0 = (int)(fl & 0xFFu), n1 = (int)((fl >> 8) & 0xFFu), n2 = (int)((fl >> 16) & 0xFFu);
                 if (decltype(allpk)::value || !__ballot(act && !(fl & kPacked))) {
@@ -1171,9 +1231,10 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
                     const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
                     if (!__ballot(cov)) return;
-                    zkeep(R, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
+                    zkeep(R, en, qp, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
                     return;
                 }
+                const int P = (int)(qp >> 16), Q = (int)(qp & 0xFFFFu);
                 bool cov = false;
                 float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
                 if (act && (fl & kPacked)) {
@@ -1185,7 +1246,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     w1 = (float)F1 * R.rw1;
                     w2 = (float)F2 * R.rw2;
                 } else if (act && !(fl & kSlow)) {
-                    const LExt &X = sext[k];
+                    const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
                     const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
                     const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
                     const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
@@ -1194,7 +1255,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     w1 = (float)F1 * R.rw1;
                     w2 = (float)F2 * R.rw2;
                 } else if (act) {
-                    const LExt &X = sext[k];
+                    const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
                     const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
                     const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
                     const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
@@ -1204,68 +1265,66 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     w2 = (float)E2 * R.rw2;
                 }
                 if (!__ballot(cov)) return;
-                zkeep(R, cov, w0, w1, w2);
+                zkeep(R, en, qp, cov, w0, w1, w2);
             };
-            // the wave's NL blocks (8 or 16 lanes each) walk their own lists
-            // of records whose box touches them: one step tests up to NL
-            // records.  Block b of this wave is bit qb + (b / 2) NX + b % 2
-            // of a record's block mask.  Per chunk of 64 records, each
-            // block's relevant records are compacted into its LDS list; step
-            // i then tests entry i of every block's list.
+            // Per 64 records, the wave lists the (record, block) pairs of the
+            // records whose block mask has its blocks (block b of this wave
+            // is bit qb + (b / 2) NX + b % 2 of the mask), record by record;
+            // step i gives lane group g pair i NG + g, so every step tests
+            // NG pairs whatever blocks they fall in.  A pair entry carries
+            // the record's offset in srec (in 16-byte units, bits 12..23)
+            // and its block's pixel offsets: for the packed (Q, P) pair and
+            // for the z-keys (kPairQP, kPairZ bits).
             const uint32_t qb = (uint32_t)(sy * (8 / B::H) * B::NX + 2 * sx);
-            const uint32_t lq = ((lane >> (3 + B::HL)) << 1) | ((lane >> 2) & 1u);
-            uint32_t *const wl = &slist[wave][0][0];
+            uint32_t *const wl = &slist[wave][0];
+            const uint32_t gi = lane / GS;
             for (uint32_t g = 0; g < m; g += 64) {
                 const bool in = g + lane < m;
                 const QM qm = in ? sqm[g + lane] : (QM)0;
-                bool rl[NL];
-                unsigned long long mk[NL], any = 0;
+                uint32_t mb = 0;
+#pragma unroll
+                for (int b = 0; b < NL; ++b)
+                    mb |= (uint32_t)((qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u) << b;
+                // exclusive prefix of the pair counts over the wave, by bit
+                // planes (a count is at most NL <= 8)
+                const uint32_t np = (uint32_t)__popc(mb);
+                uint32_t pre = 0, tot = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const unsigned long long bk = __ballot((np >> k) & 1u);
+                    pre += (uint32_t)__popcll(bk & lt) << k;
+                    tot += (uint32_t)__popcll(bk) << k;
+                }
+                tot = uniform(tot);
+                if (!tot) continue;
+                const uint32_t eb = ((g + lane) * (uint32_t)(sizeof(LRec) / 16)) << 12;
 #pragma unroll
                 for (int b = 0; b < NL; ++b) {
-                    rl[b] = (qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u;
-                    mk[b] = __ballot(rl[b]);
-                    any |= mk[b];
+                    if ((mb >> b) & 1u) wl[pre++] = eb | pair_bits<TS>(b);
                 }
-                if (!any) continue;
-                const uint32_t off = (g + lane) * (uint32_t)sizeof(LRec);
-                bool rel = false;
-                uint32_t nsteps = 0, myc = 0;
-#pragma unroll
-                for (int b = 0; b < NL; ++b) {
-                    if (rl[b]) wl[b * 64 + __popcll(mk[b] & lt)] = off;
-                    rel = rel || rl[b];
-                    const uint32_t c = (uint32_t)__popcll(mk[b]);
-                    nsteps = max(nsteps, c);
-                    myc = lq == (uint32_t)b ? c : myc;
-                }
-                nsteps = uniform(nsteps);
                 // does every record this wave will test have the packed form?
-                const bool allpk = !__ballot(rel && !(srec[g + lane].flags & kPacked));
+                const bool allpk = !__ballot(mb && !(srec[g + lane].flags & kPacked));
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                const uint32_t *const myl = wl + lq * 64;
-                const char *const rb = reinterpret_cast<const char *>(srec);
+                uint32_t p = 0;
                 if (allpk) {
-                    // two steps per list read (one 8-byte LDS load)
-                    uint32_t i = 0;
-                    for (; i + 1 < nsteps; i += 2) {
-                        const uint2 o2 = *reinterpret_cast<const uint2 *>(myl + i);
-                        visit(lds_rec_at(rb, o2.x), o2.x / (uint32_t)sizeof(LRec), i < myc, std::true_type());
-                        visit(lds_rec_at(rb, o2.y), o2.y / (uint32_t)sizeof(LRec), i + 1 < myc, std::true_type());
+                    // two steps per list read (one 8-byte LDS load) while
+                    // more than NG pairs remain
+                    for (; p + NG < tot; p += 2 * NG) {
+                        const uint32_t q = p + 2 * gi;
+                        const uint2 e2 = *reinterpret_cast<const uint2 *>(wl + q);
+                        visit(e2.x, q < tot, std::true_type());
+                        visit(e2.y, q + 1 < tot, std::true_type());
                     }
-                    if (i < nsteps) {
-                        const uint32_t o = myl[i];
-                        visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::true_type());
-                    }
+                    if (p < tot) visit(wl[p + gi], p + gi < tot, std::true_type());
                 } else {
-                    for (uint32_t i = 0; i < nsteps; ++i) {
-                        const uint32_t o = myl[i];
-                        visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::false_type());
-                    }
+                    for (; p < tot; p += NG) visit(wl[p + gi], p + gi < tot, std::false_type());
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
             __syncthreads();
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const unsigned long long best = zw[lane];
         partial[(size_t)item * NT + tid] = make_uint2((uint32_t)(best >> 32), ~(uint32_t)best);
         if (v.count_work && lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
     }
