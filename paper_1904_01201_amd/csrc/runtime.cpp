@@ -539,7 +539,8 @@ Footprint footprint(const ViewReq *v, uint32_t n, const PlanOpts &o, hab_context
                  items * 8ull * (1 + (uint64_t)ts * ts);
     }
     f.desc_bytes = n * (sizeof(DView) + 32) + 4096;
-    f.arena_bytes = bytes + f.desc_bytes + 16 * 256;
+    // + the work queues and the padding of the plan's 24 aligned arrays
+    f.arena_bytes = bytes + f.desc_bytes + sizeof(DQueue) + 32 * 256;
     (void)tiles;
     return f;
 }
