@@ -273,6 +273,9 @@ def main():
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the batched path (warmup + steps), for profiler runs")
+    ap.add_argument("--one-sequence", action="store_true",
+                    help="with --profile-only: render each step as one launch sequence "
+                         "(every kernel alone on the GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run plain 256 MiB device copies (reference for FETCH/WRITE_SIZE)")
     ap.add_argument("--serve", action="store_true",
@@ -325,9 +328,11 @@ def main():
         for e in range(E):
             views[e].pose = B.pose_to_c(p[e])
 
+    one_seq = a.profile_only and a.one_sequence
+
     def batch_step(step):
         set_poses(step)
-        ctx.render_batch(None, views=views, tile_size=a.tile_size)
+        ctx.render_batch(None, views=views, tile_size=a.tile_size, one_sequence=one_seq)
 
     # ---------------------------------------------------- autotune (untimed)
     tuned = None

@@ -547,7 +547,13 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const DView *__restrict__ vie
                 for (int k = 0; k < kPer; ++k) {
                     const uint32_t i = tid + (uint32_t)k * kBinBlock;
                     c[k] = i < nt ? hist[swz(i)] & 0xFFFFu : 0u;
-                    off[k] = i < nt ? tile_off[tile_base + i] : kOverflow;
+                }
+                // list offsets of the tiles this chunk touches only (a chunk
+                // of consecutive survivors touches a small part of the view)
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t i = tid + (uint32_t)k * kBinBlock;
+                    off[k] = c[k] ? tile_off[tile_base + i] : kOverflow;
                 }
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) {
