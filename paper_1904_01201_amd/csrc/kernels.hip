@@ -866,15 +866,20 @@ __device__ __forceinline__ bool build_rec(const DView &v, uint32_t key, int ti0,
             chi[k] = clo[k] >> 31;
         }
     } else {
-        constexpr long long PM = 256ll * (TS - 1);
+        constexpr unsigned long long PM = 256ull * (TS - 1);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const long long C = (long long)dx[k] * ((long long)Oy - ay[k]) - (long long)dy[k] * ((long long)Ox - ax[k]);
+            // C_k = dy r_x - dx r_y from 32 x 32 -> 64-bit products (|r| < 2^30)
+            const long long C = (long long)dy[k] * rx[k] - (long long)dx[k] * ry[k];
             clo[k] = (int)(uint32_t)(unsigned long long)C;
             chi[k] = (int)(C >> 32);
-            const long long qx = (long long)dx[k] * PM, px = -(long long)dy[k] * PM;
-            const long long emax = C + (qx > 0 ? qx : 0) + (px > 0 ? px : 0);
-            const long long emin = C + (qx < 0 ? qx : 0) + (px < 0 ? px : 0);
+            // the largest and smallest E_k over the tile's pixel centres: C_k
+            // plus PM times the positive (negative) parts of dx_k and -dy_k
+            // (each part below 2^30 in magnitude, their sum below 2^31)
+            const uint32_t up = (uint32_t)max(dx[k], 0) + (uint32_t)(-min(dy[k], 0));
+            const uint32_t dn = (uint32_t)(-min(dx[k], 0)) + (uint32_t)max(dy[k], 0);
+            const long long emax = C + (long long)((unsigned long long)up * PM);
+            const long long emin = C - (long long)((unsigned long long)dn * PM);
             // every pixel value of the tile within +-2^29, so each product
             // term (a difference of two such values) stays within +-2^30: no
             // int32 intermediate can overflow
