@@ -99,6 +99,31 @@ def test_every_allocation_can_fail_without_leaking(room):
             return False
         return True
 
+    def split(ctx):
+        # 32 views: two launch sequences, the second with its own workspace
+        import torch
+        lib.hab_test_fail_alloc(-1)
+        h = ctx.upload_scene(sc)
+        sn = ctx.sensor(32, 32)
+        poses = np.stack([room.poses[k % room.poses.shape[0], 0] for k in range(32)])
+        ref = ctx.render(h, sn, poses, out=ctx.alloc(sn, 32, tri=True), one_sequence=True)
+        out = ctx.alloc(sn, 32, tri=True)
+        torch.cuda.synchronize()
+        lib.hab_test_fail_alloc(split.k)
+        try:
+            ctx.render(h, sn, poses, out=out)
+        except P.HabError as e:
+            assert e.status == P.HAB_ERR_OUT_OF_MEMORY
+            lib.hab_test_fail_alloc(-1)
+            ctx.render(h, sn, poses, out=out)   # the retry succeeds
+            torch.cuda.synchronize()
+            assert torch.equal(out["tri"], ref["tri"])
+            return False
+        lib.hab_test_fail_alloc(-1)
+        torch.cuda.synchronize()
+        assert torch.equal(out["tri"], ref["tri"])
+        return True
+
     def nav(ctx):
         lib.hab_test_fail_alloc(-1)
         h = ctx.upload_scene(sc)
@@ -133,6 +158,26 @@ def test_every_allocation_can_fail_without_leaking(room):
         st.close()
         return True
 
+    def split_stepper(ctx):
+        # 32 views: the graph holds two launch sequences, each with its own arena
+        lib.hab_test_fail_alloc(-1)
+        h = ctx.upload_scene(sc)
+        sn = ctx.sensor(32, 32)
+        out = ctx.alloc(sn, 32)
+        items = [(h, sn, room.poses[k, 0], out["rgb"][k], out["depth"][k], None) for k in range(32)]
+        n_before = live(lib)
+        lib.hab_test_fail_alloc(split_stepper.k)
+        try:
+            st = ctx.stepper(items)
+        except P.HabError as e:
+            assert e.status == P.HAB_ERR_OUT_OF_MEMORY
+            assert live(lib) == n_before
+            return False
+        lib.hab_test_fail_alloc(-1)
+        st.step(np.stack([room.poses[k, 0] for k in range(32)]))
+        st.close()
+        return True
+
     def server(ctx):
         lib.hab_test_fail_alloc(-1)
         h = ctx.upload_scene(sc)
@@ -152,7 +197,8 @@ def test_every_allocation_can_fail_without_leaking(room):
         srv.close()
         return True
 
-    for name, fn in (("scene upload", upload), ("render", render), ("nav_from_scene", nav), ("stepper", stepper),
+    for name, fn in (("scene upload", upload), ("render", render), ("split render", split),
+                     ("nav_from_scene", nav), ("stepper", stepper), ("split stepper", split_stepper),
                      ("server", server)):
         for k in range(40):
             fn.k = k
