@@ -181,6 +181,14 @@ typedef struct {
  * overlap on the GPU.  HAB_RENDER_ONE_SEQUENCE keeps the batch in one
  * launch sequence. */
 #define HAB_RENDER_ONE_SEQUENCE 1u
+/* Test each pixel in the lane that owns it for the whole tile, keeping its
+ * nearest fragment in that lane's registers: the atomic-free z-test (one
+ * record per pixel block per step, so a step lasts as long as the busiest
+ * block's list).  By default a wave deals (triangle, pixel block) pairs to
+ * its lane groups evenly and merges each pixel's nearest fragment in LDS by
+ * an atomic 64-bit max, the same order-free rule.  Outputs are identical. */
+#define HAB_RENDER_LANE_OWNED_Z 2u
+#define HAB_RENDER_FLAGS (HAB_RENDER_ONE_SEQUENCE | HAB_RENDER_LANE_OWNED_Z)
 typedef struct {
     uint32_t tile_size;
     float bin_factor;

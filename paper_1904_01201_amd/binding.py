@@ -30,6 +30,7 @@ HAB_ERR_TIMEOUT = 8
 HAB_NO_HIT = 0xFFFFFFFF
 OUT_RGB, OUT_DEPTH, OUT_TRI, OUT_SEMANTIC = 1, 2, 4, 8
 RENDER_ONE_SEQUENCE = 1
+RENDER_LANE_OWNED_Z = 2
 
 EXPORTED = [
     "hab_init", "hab_shutdown", "hab_status_string", "hab_get_error",

@@ -47,7 +47,8 @@ hab_status hab_init(int device, hab_context **out)
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
             ctx->cu_count = prop.multiProcessorCount;
-        for (int c = 0; c < 3; ++c) ctx->raster_bpc[c] = raster_blocks_per_cu(8 << c);
+        for (int lo = 0; lo < 2; ++lo)
+            for (int c = 0; c < 3; ++c) ctx->raster_bpc[lo][c] = raster_blocks_per_cu(8 << c, lo != 0);
         if (!dev_alloc((void **)&ctx->err, 256)) {
             delete ctx;
             return HAB_ERR_OUT_OF_MEMORY;
@@ -307,7 +308,7 @@ static hab_status render_common(hab_context *ctx, const hab_scene *scene, const 
     if (st != HAB_OK) return st;
     if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
         return HAB_ERR_INVALID_ARG;
-    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_ONE_SEQUENCE))) return HAB_ERR_INVALID_ARG;
+    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_FLAGS))) return HAB_ERR_INVALID_ARG;
     return guarded([&]() -> hab_status {
         std::vector<ViewReq> req(n);
         const size_t px = (size_t)sensor->width * sensor->height;
@@ -329,6 +330,7 @@ static hab_status render_common(hab_context *ctx, const hab_scene *scene, const 
             o.bin_factor = opts->bin_factor;
             o.tile_cap = opts->tile_cap;
             o.one_sequence = (opts->flags & HAB_RENDER_ONE_SEQUENCE) != 0;
+            o.lane_owned_z = (opts->flags & HAB_RENDER_LANE_OWNED_Z) != 0;
         }
         DeviceGuard g(ctx->device);
         if (!g.ok) return HAB_ERR_DEVICE;
@@ -360,7 +362,7 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t n,
     if (n == 0) return HAB_OK;
     if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
         return HAB_ERR_INVALID_ARG;
-    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_ONE_SEQUENCE))) return HAB_ERR_INVALID_ARG;
+    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_FLAGS))) return HAB_ERR_INVALID_ARG;
     return guarded([&]() -> hab_status {
         std::vector<ViewReq> req(n);
         for (uint32_t k = 0; k < n; ++k) {
@@ -373,6 +375,7 @@ hab_status hab_render_batch(hab_context *ctx, const hab_view *views, uint32_t n,
             o.bin_factor = opts->bin_factor;
             o.tile_cap = opts->tile_cap;
             o.one_sequence = (opts->flags & HAB_RENDER_ONE_SEQUENCE) != 0;
+            o.lane_owned_z = (opts->flags & HAB_RENDER_LANE_OWNED_Z) != 0;
         }
         DeviceGuard g(ctx->device);
         if (!g.ok) return HAB_ERR_DEVICE;

@@ -21,6 +21,7 @@ struct RasterLaunch {
     uint32_t blocks;           // total tiles
     uint32_t bands;            // total resolve bands (resolve grid)
     uint32_t grid;             // persistent raster blocks
+    bool lane_owned;           // atomic-free lane-owned z-test (else balanced steps, z-keys in LDS)
     uint64_t item_cap;         // work items the scratch below can hold
     uint2 *items;              // [item_cap] (view, tile | segment << 18)
     uint2 *partial;            // [item_cap][TS*TS] per-pixel (1/w bits, key) of each item
@@ -56,8 +57,9 @@ constexpr int kPhaseResolve = 8;
 constexpr int kProfPhases = 9;
 constexpr int kProfEvents = 2 * kProfPhases;   // start/stop per phase
 
-// Resident k_raster<ts> blocks per compute unit (sizes the persistent grid).
-int raster_blocks_per_cu(int ts);
+// Resident k_raster<ts, lane_owned> blocks per compute unit (sizes the
+// persistent grid).
+int raster_blocks_per_cu(int ts, bool lane_owned);
 
 // Enqueue the whole sequence on stream s.
 hipError_t launch_render(const LaunchPlan &L, hipStream_t s);

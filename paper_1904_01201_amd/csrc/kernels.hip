@@ -1083,7 +1083,9 @@ __device__ __forceinline__ bool resolve_tex(const DView &v, uint32_t key, int i,
     return true;
 }
 
-template <int TS>
+// LO: lane-owned pixels with an atomic-free z-test in registers; else
+// balanced steps over (record, block) pairs with the z-keys in LDS.
+template <int TS, bool LO>
 // 6 waves per SIMD: the register budget (80 VGPRs) that lets enough
 // waves hide the LDS and staging latency (the LDS of an 8-pixel tile,
 // 7.3 KB, allows 22 blocks per CU); a 32-pixel tile's LDS allows 4.
@@ -1114,19 +1116,29 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     // block) pair
     constexpr uint32_t GS = B::W * B::H, NG = 64 / GS;
     static_assert(NG == NL, "one lane group per block of a wave");
-    // per wave: the chunk's (record, block) pairs, record by record (zeroed
-    // once, so a stale entry is still a pair; padded for the last double
-    // step's read)
-    __shared__ __align__(8) uint32_t slist[NT / 64][NL * 64 + 2 * NG];
-    // per wave: the best z-key of each of its 64 pixels (row-major 8 x 8)
-    __shared__ unsigned long long szb[NT / 64][64];
+    // per wave, lane-owned pixels: per block, byte offsets in srec of the
+    // chunk's records that touch the block ([NL][64]); balanced steps: the
+    // chunk's (record, block) pairs, record by record, padded for the last
+    // double step's read (zeroed once, so a stale entry is still a record
+    // or a pair)
+    constexpr uint32_t kList = LO ? NL * 64 : NL * 64 + 2 * NG;
+    __shared__ __align__(8) uint32_t slist[NT / 64][kList];
+    // per wave, balanced steps: the best z-key of each of its 64 pixels
+    // (row-major 8 x 8)
+    __shared__ unsigned long long szb[NT / 64][LO ? 1 : 64];
     __shared__ uint32_t s_item;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const unsigned long long lt = lanemask_lt();
-    for (uint32_t i = lane; i < NL * 64 + 2 * NG; i += 64) slist[wave][i] = 0;
+    for (uint32_t i = lane; i < kList; i += 64) slist[wave][i] = 0;
     const int sx = (int)(wave % NS), sy = (int)(wave / NS);
-    // a lane's place in its group's block: (pxl, pyl); the group's block b
+    // lane-owned pixels: lane (li, lj) of the wave's 8 x 8 pixels, at (P, Q)
+    // in 1/256 pixel from the tile's first pixel centre; (Q, P) as a 16-bit
+    // pair for the packed edge records (dot2 gives dx Q - dy P)
+    const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
+    const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
+    const short2_t QP = __builtin_bit_cast(short2_t, (uint32_t)Q | ((uint32_t)P << 16));
+    // balanced steps: a lane's place in its group's block: (pxl, pyl); the group's block b
     // (bx = b % 2, by = b / 2 in the wave's 8 x 8 pixels) comes with the
     // pair.  QPl: (Q, P) of that place in block 0 as a 16-bit pair for the
     // packed edge records (dot2 gives dx Q - dy P); zl: its byte offset in
@@ -1158,6 +1170,9 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
         const int tx = (int)(tile % v.tiles_x), ty = (int)(tile / v.tiles_x);
         const int ti0 = tx * TS, tj0 = ty * TS;
         const bool count = v.count_work != 0;
+        // lane-owned pixels: the lanes whose pixel is in view
+        unsigned long long inmask = 0ull;
+        if constexpr (LO) inmask = __ballot(ti0 + sx * 8 + li < (int)v.W && tj0 + sy * 8 + lj < (int)v.H);
 
         const uint32_t tglob = v.tile_base + tile;
         const uint32_t cnt = tile_count[tglob];
@@ -1167,14 +1182,18 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
         const uint32_t end = over ? ctr[vi].surv_count : min(begin + S, cnt);
         const uint32_t *list = bins + v.bin_base + (over ? 0u : off);
 
-        // z-key of the best fragment so far at each pixel of the wave: 1/w
-        // bits above the complemented triangle key.  A covered fragment has
-        // 1/w > 0 (positive weights, positive twice-area), so one unsigned
-        // max orders by largest 1/w, then smaller key; 0 means no fragment.
-        // Any lane group may test any pixel block, so the keys are kept in
-        // LDS and merged by atomic max.
-        zw[lane] = 0ull;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // z-key of the best fragment so far: 1/w bits above the complemented
+        // triangle key.  A covered fragment has 1/w > 0 (positive weights,
+        // positive twice-area), so one unsigned max orders by largest 1/w,
+        // then smaller key; 0 means no fragment.  Lane-owned pixels keep it
+        // in the owning lane's registers (atomic-free); balanced steps, where
+        // any lane group may test any pixel block, keep it in LDS and merge
+        // by atomic max.
+        unsigned long long best = 0ull;
+        if constexpr (!LO) {
+            zw[lane] = 0ull;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
         uint32_t ncov = 0;
 
         for (uint32_t base = begin; base < end; base += NT) {
@@ -1206,136 +1225,257 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
             }
             __syncthreads();
             const uint32_t m = min((uint32_t)NT, end - base);
-            // z-test of the pixel of pair entry `en` against fragment weights
-            // w_k where covered (cov)
-            auto zkeep = [&](const LRec &R, uint32_t en, uint32_t qp, bool cov, float w0, float w1, float w2) {
-                const float num = (w0 + w1) + w2;
-                const float rho = num * R.invA;
-                const unsigned long long cand =
-                    ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
-                if (count) {
-                    // pixels outside the view do not count
-                    const bool inv = ti0 + (int)(qp >> 24) < (int)v.W && tj0 + (int)((qp & 0xFFFFu) >> 8) < (int)v.H;
-                    ncov += (uint32_t)__popcll(__ballot(cov && inv));
-                }
-                if (cov) {
-                    unsigned long long *z = reinterpret_cast<unsigned long long *>(
-                        reinterpret_cast<char *>(zw) + ((en & kPairZ<TS>) | zl));
-                    atomicMax(z, cand);
-                }
-            };
-            // one step: every active lane tests the pixel its pair entry
-            // names against the pair's record under the top-left rule (an
-            // edge not owned needs E > 0)
-            const char *const rb = reinterpret_cast<const char *>(srec);
-            auto visit = [&](uint32_t en, bool act, auto allpk) {
-                const uint32_t off = ((en >> 12) & 0xFFFu) << 4;
-                const LRec R = lds_rec_at(rb, off);
-                const uint32_t qp = (en & kPairQP<TS>) | QPl;
-                const short2_t QP = __builtin_bit_cast(short2_t, qp);
-                const uint32_t fl = R.flags;
-                const int n0 = (int)(fl & 0xFFu), n1 = (int)((fl >> 8) & 0xFFu), n2 = (int)((fl >> 16) & 0xFFu);
-                if (decltype(allpk)::value || !__ballot(act && !(fl & kPacked))) {
-                    // every active lane's record is packed
-                    const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
-                    const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
-                    const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
-                    const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
-                    if (!__ballot(cov)) return;
-                    zkeep(R, en, qp, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
-                    return;
-                }
-                const int P = (int)(qp >> 16), Q = (int)(qp & 0xFFFFu);
-                bool cov = false;
-                float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
-                if (act && (fl & kPacked)) {
-                    const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
-                    const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
-                    const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
-                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
-                    w0 = (float)F0 * R.rw0;
-                    w1 = (float)F1 * R.rw1;
-                    w2 = (float)F2 * R.rw2;
-                } else if (act && !(fl & kSlow)) {
-                    const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
-                    const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
-                    const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
-                    const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
-                    cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
-                    w0 = (float)F0 * R.rw0;
-                    w1 = (float)F1 * R.rw1;
-                    w2 = (float)F2 * R.rw2;
-                } else if (act) {
-                    const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
-                    const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
-                    const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
-                    const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
-                    cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
-                    w0 = (float)E0 * R.rw0;
-                    w1 = (float)E1 * R.rw1;
-                    w2 = (float)E2 * R.rw2;
-                }
-                if (!__ballot(cov)) return;
-                zkeep(R, en, qp, cov, w0, w1, w2);
-            };
-            // Per 64 records, the wave lists the (record, block) pairs of the
-            // records whose block mask has its blocks (block b of this wave
-            // is bit qb + (b / 2) NX + b % 2 of the mask), record by record;
-            // step i gives lane group g pair i NG + g, so every step tests
-            // NG pairs whatever blocks they fall in.  A pair entry carries
-            // the record's offset in srec (in 16-byte units, bits 12..23)
-            // and its block's pixel offsets: for the packed (Q, P) pair and
-            // for the z-keys (kPairQP, kPairZ bits).
-            const uint32_t qb = (uint32_t)(sy * (8 / B::H) * B::NX + 2 * sx);
-            uint32_t *const wl = &slist[wave][0];
-            const uint32_t gi = lane / GS;
-            for (uint32_t g = 0; g < m; g += 64) {
-                const bool in = g + lane < m;
-                const QM qm = in ? sqm[g + lane] : (QM)0;
-                uint32_t mb = 0;
-#pragma unroll
-                for (int b = 0; b < NL; ++b)
-                    mb |= (uint32_t)((qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u) << b;
-                // exclusive prefix of the pair counts over the wave, by bit
-                // planes (a count is at most NL <= 8)
-                const uint32_t np = (uint32_t)__popc(mb);
-                uint32_t pre = 0, tot = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const unsigned long long bk = __ballot((np >> k) & 1u);
-                    pre += (uint32_t)__popcll(bk & lt) << k;
-                    tot += (uint32_t)__popcll(bk) << k;
-                }
-                tot = uniform(tot);
-                if (!tot) continue;
-                const uint32_t eb = ((g + lane) * (uint32_t)(sizeof(LRec) / 16)) << 12;
-#pragma unroll
-                for (int b = 0; b < NL; ++b) {
-                    if ((mb >> b) & 1u) wl[pre++] = eb | pair_bits<TS>(b);
-                }
-                // does every record this wave will test have the packed form?
-                const bool allpk = !__ballot(mb && !(srec[g + lane].flags & kPacked));
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                uint32_t p = 0;
-                if (allpk) {
-                    // two steps per list read (one 8-byte LDS load) while
-                    // more than NG pairs remain
-                    for (; p + NG < tot; p += 2 * NG) {
-                        const uint32_t q = p + 2 * gi;
-                        const uint2 e2 = *reinterpret_cast<const uint2 *>(wl + q);
-                        visit(e2.x, q < tot, std::true_type());
-                        visit(e2.y, q + 1 < tot, std::true_type());
+            if constexpr (LO) {
+                // z-test of this lane's pixel against fragment weights w_k where
+                // covered (cov) and the wave's coverage ballot cm
+                auto zkeep = [&](const LRec &R, bool cov, float w0, float w1, float w2) {
+                    const float num = (w0 + w1) + w2;
+                    const float rho = num * R.invA;
+                    const unsigned long long cand =
+                        ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
+                    if (count) ncov += (uint32_t)__popcll(__ballot(cov) & inmask);
+                    best = (cov && cand > best) ? cand : best;
+                };
+                // one step: every active lane tests its pixel against record R
+                // (index k) of its block under the top-left rule (an edge not
+                // owned needs E > 0)
+                auto visit = [&](const LRec &R, uint32_t k, bool act, auto allpk) {
+                    const uint32_t fl = R.flags;
+                    const int n0 = (int)(fl & 0xFFu), n1 = (int)((fl >> 8) & 0xFFu), n2 = (int)((fl >> 16) & 0xFFu);
+                    if (decltype(allpk)::value || !__ballot(act && !(fl & kPacked))) {
+                        // every active lane's record is packed
+                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                        const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
+                        if (!__ballot(cov)) return;
+                        zkeep(R, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
+                        return;
                     }
-                    if (p < tot) visit(wl[p + gi], p + gi < tot, std::true_type());
-                } else {
-                    for (; p < tot; p += NG) visit(wl[p + gi], p + gi < tot, std::false_type());
+                    bool cov = false;
+                    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+                    if (act && (fl & kPacked)) {
+                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                        cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                        w0 = (float)F0 * R.rw0;
+                        w1 = (float)F1 * R.rw1;
+                        w2 = (float)F2 * R.rw2;
+                    } else if (act && !(fl & kSlow)) {
+                        const LExt &X = sext[k];
+                        const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
+                        const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
+                        const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
+                        cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                        w0 = (float)F0 * R.rw0;
+                        w1 = (float)F1 * R.rw1;
+                        w2 = (float)F2 * R.rw2;
+                    } else if (act) {
+                        const LExt &X = sext[k];
+                        const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
+                        const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
+                        const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
+                        cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
+                        w0 = (float)E0 * R.rw0;
+                        w1 = (float)E1 * R.rw1;
+                        w2 = (float)E2 * R.rw2;
+                    }
+                    if (!__ballot(cov)) return;
+                    zkeep(R, cov, w0, w1, w2);
+                };
+                // the wave's NL blocks (8 or 16 lanes each) walk their own lists
+                // of records whose box touches them: one step tests up to NL
+                // records.  Block b of this wave is bit qb + (b / 2) NX + b % 2
+                // of a record's block mask.  Per chunk of 64 records, each
+                // block's relevant records are compacted into its LDS list; step
+                // i then tests entry i of every block's list.
+                const uint32_t qb = (uint32_t)(sy * (8 / B::H) * B::NX + 2 * sx);
+                const uint32_t lq = ((lane >> (3 + B::HL)) << 1) | ((lane >> 2) & 1u);
+                uint32_t *const wl = &slist[wave][0];
+                for (uint32_t g = 0; g < m; g += 64) {
+                    const bool in = g + lane < m;
+                    const QM qm = in ? sqm[g + lane] : (QM)0;
+                    bool rl[NL];
+                    unsigned long long mk[NL], any = 0;
+    #pragma unroll
+                    for (int b = 0; b < NL; ++b) {
+                        rl[b] = (qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u;
+                        mk[b] = __ballot(rl[b]);
+                        any |= mk[b];
+                    }
+                    if (!any) continue;
+                    const uint32_t off = (g + lane) * (uint32_t)sizeof(LRec);
+                    bool rel = false;
+                    uint32_t nsteps = 0, myc = 0;
+    #pragma unroll
+                    for (int b = 0; b < NL; ++b) {
+                        if (rl[b]) wl[b * 64 + __popcll(mk[b] & lt)] = off;
+                        rel = rel || rl[b];
+                        const uint32_t c = (uint32_t)__popcll(mk[b]);
+                        nsteps = max(nsteps, c);
+                        myc = lq == (uint32_t)b ? c : myc;
+                    }
+                    nsteps = uniform(nsteps);
+                    // does every record this wave will test have the packed form?
+                    const bool allpk = !__ballot(rel && !(srec[g + lane].flags & kPacked));
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    const uint32_t *const myl = wl + lq * 64;
+                    const char *const rb = reinterpret_cast<const char *>(srec);
+                    if (allpk) {
+                        // two steps per list read (one 8-byte LDS load)
+                        uint32_t i = 0;
+                        for (; i + 1 < nsteps; i += 2) {
+                            const uint2 o2 = *reinterpret_cast<const uint2 *>(myl + i);
+                            visit(lds_rec_at(rb, o2.x), o2.x / (uint32_t)sizeof(LRec), i < myc, std::true_type());
+                            visit(lds_rec_at(rb, o2.y), o2.y / (uint32_t)sizeof(LRec), i + 1 < myc, std::true_type());
+                        }
+                        if (i < nsteps) {
+                            const uint32_t o = myl[i];
+                            visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::true_type());
+                        }
+                    } else {
+                        for (uint32_t i = 0; i < nsteps; ++i) {
+                            const uint32_t o = myl[i];
+                            visit(lds_rec_at(rb, o), o / (uint32_t)sizeof(LRec), i < myc, std::false_type());
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            } else {
+                // z-test of the pixel of pair entry `en` against fragment weights
+                // w_k where covered (cov)
+                auto zkeep = [&](const LRec &R, uint32_t en, uint32_t qp, bool cov, float w0, float w1, float w2) {
+                    const float num = (w0 + w1) + w2;
+                    const float rho = num * R.invA;
+                    const unsigned long long cand =
+                        ((unsigned long long)__float_as_uint(rho) << 32) | (unsigned long long)R.nkey;
+                    if (count) {
+                        // pixels outside the view do not count
+                        const bool inv = ti0 + (int)(qp >> 24) < (int)v.W && tj0 + (int)((qp & 0xFFFFu) >> 8) < (int)v.H;
+                        ncov += (uint32_t)__popcll(__ballot(cov && inv));
+                    }
+                    if (cov) {
+                        unsigned long long *z = reinterpret_cast<unsigned long long *>(
+                            reinterpret_cast<char *>(zw) + ((en & kPairZ<TS>) | zl));
+                        atomicMax(z, cand);
+                    }
+                };
+                // one step: every active lane tests the pixel its pair entry
+                // names against the pair's record under the top-left rule (an
+                // edge not owned needs E > 0)
+                const char *const rb = reinterpret_cast<const char *>(srec);
+                auto visit = [&](uint32_t en, bool act, auto allpk) {
+                    const uint32_t off = ((en >> 12) & 0xFFFu) << 4;
+                    const LRec R = lds_rec_at(rb, off);
+                    const uint32_t qp = (en & kPairQP<TS>) | QPl;
+                    const short2_t QP = __builtin_bit_cast(short2_t, qp);
+                    const uint32_t fl = R.flags;
+                    const int n0 = (int)(fl & 0xFFu), n1 = (int)((fl >> 8) & 0xFFu), n2 = (int)((fl >> 16) & 0xFFu);
+                    if (decltype(allpk)::value || !__ballot(act && !(fl & kPacked))) {
+                        // every active lane's record is packed
+                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                        const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
+                        if (!__ballot(cov)) return;
+                        zkeep(R, en, qp, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
+                        return;
+                    }
+                    const int P = (int)(qp >> 16), Q = (int)(qp & 0xFFFFu);
+                    bool cov = false;
+                    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+                    if (act && (fl & kPacked)) {
+                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
+                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
+                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                        cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                        w0 = (float)F0 * R.rw0;
+                        w1 = (float)F1 * R.rw1;
+                        w2 = (float)F2 * R.rw2;
+                    } else if (act && !(fl & kSlow)) {
+                        const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
+                        const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
+                        const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
+                        const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
+                        cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
+                        w0 = (float)F0 * R.rw0;
+                        w1 = (float)F1 * R.rw1;
+                        w2 = (float)F2 * R.rw2;
+                    } else if (act) {
+                        const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
+                        const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
+                        const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
+                        const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
+                        cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
+                        w0 = (float)E0 * R.rw0;
+                        w1 = (float)E1 * R.rw1;
+                        w2 = (float)E2 * R.rw2;
+                    }
+                    if (!__ballot(cov)) return;
+                    zkeep(R, en, qp, cov, w0, w1, w2);
+                };
+                // Per 64 records, the wave lists the (record, block) pairs of the
+                // records whose block mask has its blocks (block b of this wave
+                // is bit qb + (b / 2) NX + b % 2 of the mask), record by record;
+                // step i gives lane group g pair i NG + g, so every step tests
+                // NG pairs whatever blocks they fall in.  A pair entry carries
+                // the record's offset in srec (in 16-byte units, bits 12..23)
+                // and its block's pixel offsets: for the packed (Q, P) pair and
+                // for the z-keys (kPairQP, kPairZ bits).
+                const uint32_t qb = (uint32_t)(sy * (8 / B::H) * B::NX + 2 * sx);
+                uint32_t *const wl = &slist[wave][0];
+                const uint32_t gi = lane / GS;
+                for (uint32_t g = 0; g < m; g += 64) {
+                    const bool in = g + lane < m;
+                    const QM qm = in ? sqm[g + lane] : (QM)0;
+                    uint32_t mb = 0;
+    #pragma unroll
+                    for (int b = 0; b < NL; ++b)
+                        mb |= (uint32_t)((qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u) << b;
+                    // exclusive prefix of the pair counts over the wave, by bit
+                    // planes (a count is at most NL <= 8)
+                    const uint32_t np = (uint32_t)__popc(mb);
+                    uint32_t pre = 0, tot = 0;
+    #pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const unsigned long long bk = __ballot((np >> k) & 1u);
+                        pre += (uint32_t)__popcll(bk & lt) << k;
+                        tot += (uint32_t)__popcll(bk) << k;
+                    }
+                    tot = uniform(tot);
+                    if (!tot) continue;
+                    const uint32_t eb = ((g + lane) * (uint32_t)(sizeof(LRec) / 16)) << 12;
+    #pragma unroll
+                    for (int b = 0; b < NL; ++b) {
+                        if ((mb >> b) & 1u) wl[pre++] = eb | pair_bits<TS>(b);
+                    }
+                    // does every record this wave will test have the packed form?
+                    const bool allpk = !__ballot(mb && !(srec[g + lane].flags & kPacked));
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    uint32_t p = 0;
+                    if (allpk) {
+                        // two steps per list read (one 8-byte LDS load) while
+                        // more than NG pairs remain
+                        for (; p + NG < tot; p += 2 * NG) {
+                            const uint32_t q = p + 2 * gi;
+                            const uint2 e2 = *reinterpret_cast<const uint2 *>(wl + q);
+                            visit(e2.x, q < tot, std::true_type());
+                            visit(e2.y, q + 1 < tot, std::true_type());
+                        }
+                        if (p < tot) visit(wl[p + gi], p + gi < tot, std::true_type());
+                    } else {
+                        for (; p < tot; p += NG) visit(wl[p + gi], p + gi < tot, std::false_type());
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                }
             }
             __syncthreads();
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const unsigned long long best = zw[lane];
+        if constexpr (!LO) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            best = zw[lane];
+        }
         partial[(size_t)item * NT + tid] = make_uint2((uint32_t)(best >> 32), ~(uint32_t)best);
         if (v.count_work && lane == 0 && ncov) atomicAdd(&ctr[vi].covered, (unsigned long long)ncov);
     }
@@ -1487,8 +1627,12 @@ static inline void mark(const LaunchPlan &L, int ev, hipStream_t s)
 template <int TS>
 static void launch_raster(const LaunchPlan &L, const RasterLaunch &R, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_raster<TS>, dim3(R.grid), dim3(TS * TS), 0, s, L.views, R.items, L.queue,
-                       L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins, R.partial, L.err);
+    if (R.lane_owned)
+        hipLaunchKernelGGL((k_raster<TS, true>), dim3(R.grid), dim3(TS * TS), 0, s, L.views, R.items, L.queue,
+                           L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins, R.partial, L.err);
+    else
+        hipLaunchKernelGGL((k_raster<TS, false>), dim3(R.grid), dim3(TS * TS), 0, s, L.views, R.items, L.queue,
+                           L.ctr, L.skey, L.sbox, L.tile_count, L.tile_off, L.bins, R.partial, L.err);
 }
 
 template <int TS>
@@ -1498,14 +1642,17 @@ static void launch_resolve(const LaunchPlan &L, const RasterLaunch &R, hipStream
                        R.nl, L.tile_count, L.tile_off, L.tile_item, R.partial, L.err);
 }
 
-int raster_blocks_per_cu(int ts)
+int raster_blocks_per_cu(int ts, bool lane_owned)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
-    switch (ts) {
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<8>, 64, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<16>, 256, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<32>, 1024, 0); break;
+    switch (ts * 2 + (lane_owned ? 1 : 0)) {
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<8, false>, 64, 0); break;
+    case 17: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<8, true>, 64, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<16, false>, 256, 0); break;
+    case 33: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<16, true>, 256, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<32, false>, 1024, 0); break;
+    case 65: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_raster<32, true>, 1024, 0); break;
     default: break;
     }
     if (e != hipSuccess) (void)hipGetLastError();

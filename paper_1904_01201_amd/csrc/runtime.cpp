@@ -477,9 +477,10 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
     L.bin_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ub, 8ull * (ctx ? ctx->cu_count : 256)));
     L.nraster = 0;
     const uint32_t cus = ctx ? (uint32_t)ctx->cu_count : 256u;
-    const uint32_t kBlocksPerCu[3] = {ctx ? (uint32_t)ctx->raster_bpc[0] : 1u,
-                                      ctx ? (uint32_t)ctx->raster_bpc[1] : 1u,
-                                      ctx ? (uint32_t)ctx->raster_bpc[2] : 1u};
+    const int lo = o.lane_owned_z ? 1 : 0;
+    const uint32_t kBlocksPerCu[3] = {ctx ? (uint32_t)ctx->raster_bpc[lo][0] : 1u,
+                                      ctx ? (uint32_t)ctx->raster_bpc[lo][1] : 1u,
+                                      ctx ? (uint32_t)ctx->raster_bpc[lo][2] : 1u};
     for (int c = 0; c < 3; ++c) {
         if (lview[c].empty()) continue;
         RasterLaunch &R = L.raster[L.nraster++];
@@ -491,6 +492,7 @@ hab_status build_plan(hab_context *ctx, Workspace &ws, const ViewReq *v, uint32_
         R.bands = lpre[c].back() + cdiv(last.W, 32u) * cdiv(last.H, 2u);
         R.item_cap = item_cap[c];
         R.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(item_cap[c], (uint64_t)cus * kBlocksPerCu[c]));
+        R.lane_owned = o.lane_owned_z;
     }
     return HAB_OK;
 }

@@ -92,6 +92,7 @@ struct PlanOpts {
     uint32_t tile_cap = 0;      // 0: unlimited
     bool count_work = false;    // accumulate bbox tests / covered fragments
     bool one_sequence = false;  // never split a batch into two launch sequences
+    bool lane_owned_z = false;  // the atomic-free lane-owned z-test
 };
 
 // Sizes of one launch sequence; used for memory admission as well.
@@ -183,7 +184,8 @@ struct hab_context {
     std::vector<habmi::Tuned> tuned;  // autotune table
     std::mutex tune_mu;
     int cu_count = 256;
-    int raster_bpc[3] = {1, 1, 1};    // resident raster blocks per CU, tile 8/16/32
+    // resident raster blocks per CU: [lane-owned z-test][tile 8/16/32]
+    int raster_bpc[2][3] = {{1, 1, 1}, {1, 1, 1}};
     // per-phase event timing (hab_profile_enable)
     struct ProfSet {
         hipEvent_t ev[habmi::kProfEvents];

@@ -109,7 +109,7 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
     if (!ctx || !views || !out || n == 0 || n > kMaxViews) return HAB_ERR_INVALID_ARG;
     if (opts && opts->tile_size && opts->tile_size != 8 && opts->tile_size != 16 && opts->tile_size != 32)
         return HAB_ERR_INVALID_ARG;
-    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_ONE_SEQUENCE))) return HAB_ERR_INVALID_ARG;
+    if (opts && (opts->bin_factor < 0.0f || (opts->flags & ~HAB_RENDER_FLAGS))) return HAB_ERR_INVALID_ARG;
     *out = nullptr;
     try {
         int prev = -1;
@@ -132,6 +132,7 @@ hab_status hab_stepper_create(hab_context *ctx, const hab_view *views, uint32_t 
             o.tile_size = opts->tile_size;
             o.bin_factor = opts->bin_factor;
             o.tile_cap = opts->tile_cap;
+            o.lane_owned_z = (opts->flags & HAB_RENDER_LANE_OWNED_Z) != 0;
         }
         auto fail = [&](hab_status e) {
             destroy(st);

@@ -174,9 +174,9 @@ class Context:
         return out
 
     @staticmethod
-    def _opts(tile_size=0, bin_factor=0.0, tile_cap=0, stats=None, one_sequence=False):
-        o = B.RenderOpts(int(tile_size), float(bin_factor), int(tile_cap),
-                         B.RENDER_ONE_SEQUENCE if one_sequence else 0, None)
+    def _opts(tile_size=0, bin_factor=0.0, tile_cap=0, stats=None, one_sequence=False, lane_owned_z=False):
+        flags = (B.RENDER_ONE_SEQUENCE if one_sequence else 0) | (B.RENDER_LANE_OWNED_Z if lane_owned_z else 0)
+        o = B.RenderOpts(int(tile_size), float(bin_factor), int(tile_cap), flags, None)
         if stats is not None:
             o.stats = C.cast(stats, C.POINTER(B.ViewStats))
         return o
@@ -184,7 +184,7 @@ class Context:
     # ------------------------------------------------------------ render
     def render(self, scene: SceneHandle, sensor: B.Sensor, poses, rgb=None, depth=None, tri=None,
                tile_size=0, bin_factor=0.0, tile_cap=0, stats=False, stream=None, out=None,
-               one_sequence=False):
+               one_sequence=False, lane_owned_z=False):
         """Render N views of one scene.  Returns dict of output tensors (and
         'stats': list of dicts if requested).  A sensor with the semantic
         output goes through hab_render_batch (one view per pose, noise seed =
@@ -209,12 +209,12 @@ class Context:
                                                  for name in ("rgb", "depth", "tri", "semantic")], k)
                      for k in range(n)]
             st = self.render_batch(items, tile_size, bin_factor, tile_cap, stats, stream,
-                                   one_sequence=one_sequence)
+                                   one_sequence=one_sequence, lane_owned_z=lane_owned_z)
             if stats:
                 out["stats"] = st
             return out
         st = (B.ViewStats * n)() if stats else None
-        o = self._opts(tile_size, bin_factor, tile_cap, st, one_sequence)
+        o = self._opts(tile_size, bin_factor, tile_cap, st, one_sequence, lane_owned_z)
         pc = B.poses_to_c(poses)
         B.check(self.lib.hab_render_ex(self.h, C.c_void_p(scene.ptr), C.byref(sensor), pc, n,
                                        _ptr(out.get("rgb")), _ptr(out.get("depth")),
@@ -274,14 +274,15 @@ class Context:
         return arr
 
     def render_batch(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stats=False, stream=None,
-                     views=None, one_sequence=False):
+                     views=None, one_sequence=False, lane_owned_z=False):
         """Render a list of views (or prepared hab_view records, `views`).
         32 or more views run as two launch sequences side by side unless
-        one_sequence."""
+        one_sequence; lane_owned_z selects the atomic-free lane-owned
+        z-test (same outputs)."""
         arr = views if views is not None else self.make_views(items)
         n = len(arr)
         st = (B.ViewStats * n)() if stats else None
-        o = self._opts(tile_size, bin_factor, tile_cap, st, one_sequence)
+        o = self._opts(tile_size, bin_factor, tile_cap, st, one_sequence, lane_owned_z)
         B.check(self.lib.hab_render_batch(self.h, arr, n, C.byref(o), _stream_ptr(stream)),
                 "hab_render_batch")
         if stats:
@@ -397,8 +398,9 @@ class Context:
                                      _stream_ptr(stream)), "hab_actuate")
 
     # ------------------------------------------------------------ stepper
-    def stepper(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None, one_sequence=False):
-        return Stepper(self, items, tile_size, bin_factor, tile_cap, stream, one_sequence)
+    def stepper(self, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None, one_sequence=False,
+                lane_owned_z=False):
+        return Stepper(self, items, tile_size, bin_factor, tile_cap, stream, one_sequence, lane_owned_z)
 
     # ------------------------------------------------------------ autotune
     def autotune(self, items, stream=None):
@@ -413,10 +415,11 @@ class Stepper:
     """A fixed batch composition captured as a HIP graph; step(poses)."""
 
     def __init__(self, ctx: Context, items, tile_size=0, bin_factor=0.0, tile_cap=0, stream=None,
-                 one_sequence=False):
+                 one_sequence=False, lane_owned_z=False):
         self.ctx = ctx
         self.views = ctx.make_views(items)
-        o = Context._opts(tile_size, bin_factor, tile_cap, one_sequence=one_sequence)
+        o = Context._opts(tile_size, bin_factor, tile_cap, one_sequence=one_sequence,
+                          lane_owned_z=lane_owned_z)
         h = C.c_void_p()
         B.check(ctx.lib.hab_stepper_create(ctx.h, self.views, len(self.views), C.byref(o),
                                            _stream_ptr(stream), C.byref(h)), "hab_stepper_create")

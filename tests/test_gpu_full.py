@@ -3,8 +3,9 @@
 The 64-environment batch (4 jittered apartments of 100k-1M triangles,
 256x256 RGB+D) is one hab_render_batch call per step; it runs at each tile
 size the autotuner may pick (8, 16 and 32 pixels), with the autotuner's own
-choice, and through the lossless overflow path (a tile capacity of 64 list
-entries; a bin capacity of a quarter of the triangle count).  The
+choice, through the lossless overflow path (a tile capacity of 64 list
+entries; a bin capacity of a quarter of the triangle count), and with the
+atomic-free lane-owned z-test instead of the default balanced steps.  The
 256-environment mixed batch (16 apartments of 50k-1.5M triangles, 128/256/
 512 px, depth / RGB / RGB+D sensors) runs through the captured stepper at
 the default tile and at 8 and 32 pixels.  One view per environment every
@@ -53,6 +54,10 @@ BATCH64_OPTS = [
     ("tile8_cap64", {"tile_size": 8, "tile_cap": 64}),
     ("tile8_bins0.25", {"tile_size": 8, "bin_factor": 0.25}),
     ("autotuned", None),
+    # the atomic-free lane-owned z-test (HAB_RENDER_LANE_OWNED_Z)
+    ("tile8_lane_owned", {"tile_size": 8, "lane_owned_z": True}),
+    ("tile32_lane_owned", {"tile_size": 32, "lane_owned_z": True}),
+    ("tile8_cap64_lane_owned", {"tile_size": 8, "tile_cap": 64, "lane_owned_z": True}),
 ]
 
 

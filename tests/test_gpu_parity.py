@@ -215,6 +215,49 @@ def test_split_batch_equals_alone(ctx):
     ctx.release(s_apt)
 
 
+def test_lane_owned_and_balanced_z_tests_agree(ctx):
+    """The atomic-free lane-owned z-test (HAB_RENDER_LANE_OWNED_Z) and the
+    default balanced steps write the same bits at every tile size, through
+    the overflow path, in the stepper, and match the oracle's work counters."""
+    import torch
+    note("lane-owned vs balanced z-test")
+    room = configs.room_2k_128()
+    apt = make_apartment(seed=79, target_T=60_000)
+    s_room, s_apt = ctx.upload_scene(room.scenes[0]), ctx.upload_scene(apt)
+    poses_apt = random_walks(apt, 8, 3, seed=7)[-1]
+    cases = [(s_room, room.scenes[0], room.poses[:8, 0]), (s_apt, apt, poses_apt)]
+    for h, sc, poses in cases:
+        for W, H in ((128, 128), (200, 136)):
+            sn = ctx.sensor(W, H)
+            for opts in ({"tile_size": 8}, {"tile_size": 16}, {"tile_size": 32},
+                         {"tile_size": 8, "tile_cap": 4}):
+                a = ctx.render(h, sn, poses, out=ctx.alloc(sn, len(poses), tri=True), stats=True, **opts)
+                b = ctx.render(h, sn, poses, out=ctx.alloc(sn, len(poses), tri=True), stats=True,
+                               lane_owned_z=True, **opts)
+                torch.cuda.synchronize()
+                for k in ("rgb", "depth", "tri"):
+                    assert torch.equal(a[k], b[k]), (W, H, opts, k)
+                assert a["stats"] == b["stats"], (W, H, opts)
+            o = oracle.render_view(sc.positions, sc.colors, sc.indices, W, H, poses[0])
+            assert b["stats"][0]["covered"] == o["stats"]["covered"]
+            assert np.array_equal(b["tri"].cpu().numpy()[0].view(np.uint32), o["tri"])
+    # the stepper with the lane-owned z-test equals the eager default
+    sn = ctx.sensor(128, 128)
+    outs = [ctx.alloc(sn, 1, tri=True) for _ in range(4)]
+    items = [(s_room, sn, room.poses[k, 0], o_["rgb"], o_["depth"], o_["tri"]) for k, o_ in enumerate(outs)]
+    st = ctx.stepper(items, lane_owned_z=True)
+    st.step(room.poses[10:14, 0])
+    torch.cuda.synchronize()
+    for k, o_ in enumerate(outs):
+        ref = ctx.render(s_room, sn, room.poses[10 + k, 0], out=ctx.alloc(sn, 1, tri=True))
+        torch.cuda.synchronize()
+        for name in ("rgb", "depth", "tri"):
+            assert torch.equal(o_[name], ref[name]), (k, name)
+    st.close()
+    ctx.release(s_room)
+    ctx.release(s_apt)
+
+
 def test_stepper_graph_replay(ctx):
     """Graph-captured steps: each replay (new poses) equals an eager batch
     render of the same poses; eager work runs between replays."""
@@ -296,7 +339,7 @@ def test_argument_errors(ctx):
     # an unknown launch-option flag, on every entry point that takes options
     import ctypes as C
     from paper_1904_01201_amd import binding as B
-    good, bad = B.RenderOpts(0, 0.0, 0, 1, None), B.RenderOpts(0, 0.0, 0, 2, None)
+    good, bad = B.RenderOpts(0, 0.0, 0, 3, None), B.RenderOpts(0, 0.0, 0, 4, None)
     o = ctx.alloc(s, 1)
     views = ctx.make_views([(sc, s, pose_at(0, 0, 0), o["rgb"], o["depth"], None)])
     assert ctx.lib.hab_render_batch(ctx.h, views, 1, C.byref(bad), None) == P.HAB_ERR_INVALID_ARG
