@@ -400,6 +400,20 @@ def main():
     ctx.profile_phases(None)
     fps_one = E * a.steps / t_one
     log(f"batched eager, one launch sequence: {fps_one:.0f} frames/s")
+    # and with the atomic-free lane-owned z-test (same outputs)
+    ctx.profile_phases(RASTER_PHASES)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        set_poses(s)
+        ctx.render_batch(None, views=views, tile_size=a.tile_size, one_sequence=True, lane_owned_z=True)
+    torch.cuda.synchronize()
+    t_lo = time.perf_counter() - t0
+    ctx.profile(False)
+    lo_phases = ctx.profile_read()
+    ctx.profile_phases(None)
+    log(f"batched eager, one launch sequence, lane-owned z-test: {E * a.steps / t_lo:.0f} frames/s")
 
     # ---------------------------------------------------- batched (graph)
     st = ctx.stepper(items0, tile_size=a.tile_size)
@@ -567,7 +581,10 @@ def main():
                     "launch per step with no other kernel beside it (not the timed steps)",
                     "achieved": round(ops_one / (ms_one * 1e-3) / 1e12, 4), "unit": "TOP/s",
                     "frac": round(ops_one / (ms_one * 1e-3) / 1e12 / ALU_PEAK_TOPS, 5),
-                    "avg_launch_ms": round(ms_one, 5), "fps": round(fps_one, 1)}
+                    "avg_launch_ms": round(ms_one, 5), "fps": round(fps_one, 1),
+                    "lane_owned_z": {"avg_launch_ms": round(sum(lo_phases[k]["ms"] for k in raster
+                                                                if k in lo_phases) / a.steps, 5),
+                                     "fps": round(E * a.steps / t_lo, 1)}}
     else:
         roof_one = None
         byts = (geom_bytes + E * 16 * 8 if dom == "setup" else step_bytes) / lps[dom]
