@@ -1138,11 +1138,10 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
     const int li = (int)(lane & 7u), lj = (int)(lane >> 3);
     const int P = 256 * (sx * 8 + li), Q = 256 * (sy * 8 + lj);
     const short2_t QP = __builtin_bit_cast(short2_t, (uint32_t)Q | ((uint32_t)P << 16));
-    // balanced steps: a lane's place in its group's block: (pxl, pyl); the group's block b
-    // (bx = b % 2, by = b / 2 in the wave's 8 x 8 pixels) comes with the
-    // pair.  QPl: (Q, P) of that place in block 0 as a 16-bit pair for the
-    // packed edge records (dot2 gives dx Q - dy P); zl: its byte offset in
-    // the wave's z-keys.
+    // balanced steps: a lane's place in its group's block: (pxl, pyl); the
+    // group's block b (bx = b % 2, by = b / 2 in the wave's 8 x 8 pixels)
+    // comes with the pair.  QPl: (Q, P) of that place in block 0 as a
+    // 16-bit pair; zl: its byte offset in the wave's z-keys.
     const uint32_t pxl = lane % B::W, pyl = (lane % GS) / B::W;
     const uint32_t QPl = (256u * (uint32_t)(sy * 8 + (int)pyl)) | ((256u * (uint32_t)(sx * 8 + (int)pxl)) << 16);
     const uint32_t zl = (pyl * 8 + pxl) * 8;
