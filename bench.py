@@ -565,7 +565,8 @@ def main():
     if dom == "raster":
         ops = (OPS_PER_TEST * bbox_tests + OPS_PER_COVERED * covered) / lps[dom]
         ach = ops / (per_launch[dom] * 1e-3) / 1e12
-        kern = "+".join(f"k_raster<{k[6:]}>" for k in raster)
+        # the default raster form: balanced steps (k_raster<TS, false>)
+        kern = "+".join(f"k_raster<{k[6:]}, false>" for k in raster)
         tr = measured_traffic(kern)
         roof = {"kernel": kern, "bound": "alu", "achieved": round(ach, 4),
                 "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(ach / ALU_PEAK_TOPS, 5),
