@@ -324,9 +324,7 @@ def main():
     from paper_1904_01201_amd import binding as B
 
     def set_poses(step):
-        p = w.poses[step % w.num_steps]
-        for e in range(E):
-            views[e].pose = B.pose_to_c(p[e])
+        ctx.set_poses(views, w.poses[step % w.num_steps])
 
     one_seq = a.profile_only and a.one_sequence
 
@@ -502,10 +500,9 @@ def main():
             ctx.autotune(items_v)      # its own batch class (the output mix is part of the key)
 
         def step_v(step):
-            p = w.poses[step % w.num_steps]
-            for e in range(E):
-                views_v[e].pose = B.pose_to_c(p[e])
-                if noisy:
+            ctx.set_poses(views_v, w.poses[step % w.num_steps])
+            if noisy:
+                for e in range(E):
                     views_v[e].noise_seed = (step << 16) | e
             ctx.render_batch(None, views=views_v, tile_size=a.tile_size)
 

@@ -246,6 +246,19 @@ class Context:
                                             poses.shape[0], _ptr(rgb), _ptr(depth), _stream_ptr(stream)),
                 "hab_render_noalloc")
 
+    @staticmethod
+    def set_poses(views, poses):
+        """Write [n, 12] float32 poses (p[3], R[9]) into the n records of a
+        View array (from make_views) in place, all at once.  No checks here:
+        the library validates every pose when the views are rendered."""
+        p = np.ascontiguousarray(np.asarray(poses, np.float32).reshape(-1, 12))
+        n = len(views)
+        if p.shape[0] != n:
+            raise ValueError(f"{p.shape[0]} poses for {n} views")
+        raw = np.frombuffer((C.c_char * C.sizeof(views)).from_buffer(views), dtype=np.uint8)
+        off = B.View.pose.offset
+        raw.reshape(n, C.sizeof(B.View))[:, off:off + C.sizeof(B.Pose)].view(np.float32)[:] = p
+
     def make_views(self, items):
         """items: iterable of (scene, sensor, pose, rgb, depth, tri[, semantic
         [, noise_seed]]) with tensors or None.  Returns a ctypes View array

@@ -107,3 +107,20 @@ def test_output_tensor_checks():
     s = B.Sensor(8, 4, 3, 90.0, 4.0, 0.01)
     with pytest.raises(ValueError):
         check_output("depth", torch.empty(31), 1, s)      # CPU tensor / wrong size
+
+
+def test_set_poses_writes_each_record():
+    """Context.set_poses writes pose k into View record k and nothing else."""
+    n = 5
+    views = (B.View * n)()
+    for k in range(n):
+        views[k].noise_seed = 1000 + k
+    poses = np.arange(12 * n, dtype=np.float32).reshape(n, 12) * 0.5
+    P.Context.set_poses(views, poses)
+    for k in range(n):
+        assert list(views[k].pose.position) == list(poses[k, :3])
+        assert list(views[k].pose.rotation) == list(poses[k, 3:])
+        assert views[k].noise_seed == 1000 + k and not views[k].scene
+    with pytest.raises(ValueError):
+        P.Context.set_poses(views, poses[:4])
+
