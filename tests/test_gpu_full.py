@@ -179,3 +179,29 @@ def test_autotune_choice_and_invariance():
             c.release(h)
     finally:
         c.close()
+
+
+def test_batch64_z_test_forms_and_sequences_bit_identical(ctx, batch64):
+    """Every view of the full-size 64-view batch, at 8- and 32-pixel tiles:
+    the default (two launch sequences, balanced z-test), one launch
+    sequence, and the atomic-free lane-owned z-test write the same bits."""
+    import torch
+    w, hs = batch64
+    sn = ctx.sensor(256, 256)
+    for step in (0, 250, 499):
+        for ts in (8, 32):
+            note(f"batch64 step {step} tile {ts}: z-test forms and launch sequences")
+            outs = []
+            for opts in ({}, {"one_sequence": True}, {"lane_owned_z": True},
+                         {"lane_owned_z": True, "one_sequence": True}):
+                o = ctx.alloc(sn, w.num_envs, tri=True)
+                items = [(hs[w.env_scene[e]], sn, w.poses[step, e], o["rgb"][e], o["depth"][e], o["tri"][e])
+                         for e in range(w.num_envs)]
+                ctx.render_batch(items, tile_size=ts, **opts)
+                outs.append(o)
+            torch.cuda.synchronize()
+            for o in outs[1:]:
+                for k in ("rgb", "depth", "tri"):
+                    assert torch.equal(o[k], outs[0][k]), (step, ts, k)
+    assert ctx.get_error() == 0
+
