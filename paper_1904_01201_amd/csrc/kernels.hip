@@ -1297,7 +1297,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     const QM qm = in ? sqm[g + lane] : (QM)0;
                     bool rl[NL];
                     unsigned long long mk[NL], any = 0;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NL; ++b) {
                         rl[b] = (qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u;
                         mk[b] = __ballot(rl[b]);
@@ -1307,7 +1307,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     const uint32_t off = (g + lane) * (uint32_t)sizeof(LRec);
                     bool rel = false;
                     uint32_t nsteps = 0, myc = 0;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NL; ++b) {
                         if (rl[b]) wl[b * 64 + __popcll(mk[b] & lt)] = off;
                         rel = rel || rl[b];
@@ -1368,44 +1368,44 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     const uint32_t off = ((en >> 12) & 0xFFFu) << 4;
                     const LRec R = lds_rec_at(rb, off);
                     const uint32_t qp = (en & kPairQP<TS>) | QPl;
-                    const short2_t QP = __builtin_bit_cast(short2_t, qp);
+                    const short2_t QPq = __builtin_bit_cast(short2_t, qp);
                     const uint32_t fl = R.flags;
                     const int n0 = (int)(fl & 0xFFu), n1 = (int)((fl >> 8) & 0xFFu), n2 = (int)((fl >> 16) & 0xFFu);
                     if (decltype(allpk)::value || !__ballot(act && !(fl & kPacked))) {
                         // every active lane's record is packed
-                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
-                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
-                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QPq, R.c0, false);
+                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QPq, R.c1, false);
+                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QPq, R.c2, false);
                         const bool cov = act && F0 >= n0 && F1 >= n1 && F2 >= n2;
                         if (!__ballot(cov)) return;
                         zkeep(R, en, qp, cov, (float)F0 * R.rw0, (float)F1 * R.rw1, (float)F2 * R.rw2);
                         return;
                     }
-                    const int P = (int)(qp >> 16), Q = (int)(qp & 0xFFFFu);
+                    const int Pq = (int)(qp >> 16), Qq = (int)(qp & 0xFFFFu);
                     bool cov = false;
                     float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
                     if (act && (fl & kPacked)) {
-                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QP, R.c0, false);
-                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QP, R.c1, false);
-                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QP, R.c2, false);
+                        const int F0 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e0), QPq, R.c0, false);
+                        const int F1 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e1), QPq, R.c1, false);
+                        const int F2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, R.e2), QPq, R.c2, false);
                         cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
                         w0 = (float)F0 * R.rw0;
                         w1 = (float)F1 * R.rw1;
                         w2 = (float)F2 * R.rw2;
                     } else if (act && !(fl & kSlow)) {
                         const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
-                        const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Q) + (uint32_t)__mul24(X.ny0, P));
-                        const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Q) + (uint32_t)__mul24(X.ny1, P));
-                        const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Q) + (uint32_t)__mul24(X.ny2, P));
+                        const int F0 = (int)((uint32_t)R.c0 + (uint32_t)__mul24(R.e0, Qq) + (uint32_t)__mul24(X.ny0, Pq));
+                        const int F1 = (int)((uint32_t)R.c1 + (uint32_t)__mul24(R.e1, Qq) + (uint32_t)__mul24(X.ny1, Pq));
+                        const int F2 = (int)((uint32_t)R.c2 + (uint32_t)__mul24(R.e2, Qq) + (uint32_t)__mul24(X.ny2, Pq));
                         cov = F0 >= n0 && F1 >= n1 && F2 >= n2;
                         w0 = (float)F0 * R.rw0;
                         w1 = (float)F1 * R.rw1;
                         w2 = (float)F2 * R.rw2;
                     } else if (act) {
                         const LExt &X = sext[off / (uint32_t)sizeof(LRec)];
-                        const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Q + (long long)X.ny0 * P;
-                        const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Q + (long long)X.ny1 * P;
-                        const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Q + (long long)X.ny2 * P;
+                        const long long E0 = join64(X.hi0, R.c0) + (long long)R.e0 * Qq + (long long)X.ny0 * Pq;
+                        const long long E1 = join64(X.hi1, R.c1) + (long long)R.e1 * Qq + (long long)X.ny1 * Pq;
+                        const long long E2 = join64(X.hi2, R.c2) + (long long)R.e2 * Qq + (long long)X.ny2 * Pq;
                         cov = E0 >= (long long)n0 && E1 >= (long long)n1 && E2 >= (long long)n2;
                         w0 = (float)E0 * R.rw0;
                         w1 = (float)E1 * R.rw1;
@@ -1429,25 +1429,25 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                     const bool in = g + lane < m;
                     const QM qm = in ? sqm[g + lane] : (QM)0;
                     uint32_t mb = 0;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NL; ++b)
                         mb |= (uint32_t)((qm >> (qb + (uint32_t)((b >> 1) * B::NX + (b & 1)))) & 1u) << b;
                     // exclusive prefix of the pair counts over the wave, by bit
                     // planes (a count is at most NL <= 8)
                     const uint32_t np = (uint32_t)__popc(mb);
-                    uint32_t pre = 0, tot = 0;
-    #pragma unroll
+                    uint32_t pos = 0, tot = 0;
+#pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const unsigned long long bk = __ballot((np >> k) & 1u);
-                        pre += (uint32_t)__popcll(bk & lt) << k;
+                        pos += (uint32_t)__popcll(bk & lt) << k;
                         tot += (uint32_t)__popcll(bk) << k;
                     }
                     tot = uniform(tot);
                     if (!tot) continue;
                     const uint32_t eb = ((g + lane) * (uint32_t)(sizeof(LRec) / 16)) << 12;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NL; ++b) {
-                        if ((mb >> b) & 1u) wl[pre++] = eb | pair_bits<TS>(b);
+                        if ((mb >> b) & 1u) wl[pos++] = eb | pair_bits<TS>(b);
                     }
                     // does every record this wave will test have the packed form?
                     const bool allpk = !__ballot(mb && !(srec[g + lane].flags & kPacked));
@@ -1457,10 +1457,10 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 32
                         // two steps per list read (one 8-byte LDS load) while
                         // more than NG pairs remain
                         for (; p + NG < tot; p += 2 * NG) {
-                            const uint32_t q = p + 2 * gi;
-                            const uint2 e2 = *reinterpret_cast<const uint2 *>(wl + q);
-                            visit(e2.x, q < tot, std::true_type());
-                            visit(e2.y, q + 1 < tot, std::true_type());
+                            const uint32_t pi = p + 2 * gi;
+                            const uint2 e2 = *reinterpret_cast<const uint2 *>(wl + pi);
+                            visit(e2.x, pi < tot, std::true_type());
+                            visit(e2.y, pi + 1 < tot, std::true_type());
                         }
                         if (p < tot) visit(wl[p + gi], p + gi < tot, std::true_type());
                     } else {
