@@ -297,9 +297,9 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(const DView *__restrict__ v
 constexpr uint32_t kRun = 4;
 constexpr uint32_t kSetupBuf = 2 * kRun * kCluster;   // survivors one wave buffers in LDS
 
-// 5 waves per SIMD (at most 96 VGPRs, a few of them spilled): more waves
-// hide the latency of the four clusters' loads per lane better than four
-// waves without spills; at 6 waves the spills cost more than they hide
+// 5 waves per SIMD (at most 96 VGPRs; 85 used, none spilled): the four
+// clusters' loads per lane are in flight together, and at 6 waves the
+// spills cost about what the extra wave hides
 __global__ __launch_bounds__(kSetupBlock) __attribute__((amdgpu_waves_per_eu(kSetupWavesPerSimd))) void k_setup(const DView *__restrict__ views,
                                                        uint32_t nviews,
                                                        DViewCounters *__restrict__ ctr,
@@ -389,46 +389,40 @@ __global__ __launch_bounds__(kSetupBlock) __attribute__((amdgpu_waves_per_eu(kSe
                 for (int k = 0; k < 9; ++k) P[j][k] = 0.0f;
             }
         }
-        bool s[kRun][2];
-        PixBox bx[kRun][2];
+        // set up the runs' triangles one cluster at a time, appending the
+        // survivors in (cluster, sub, lane) order: only one cluster's boxes
+        // are live at once
 #pragma unroll
-        for (uint32_t j = 0; j < kRun; ++j)
-            survive(v, P[j], valid[j], s[j][0], s[j][1], bx[j][0], bx[j][1], rerr);
-        // buffer slots in (cluster, sub, lane) order
-        uint32_t cnt = 0, mine[kRun][2];
-#pragma unroll
-        for (uint32_t j = 0; j < kRun; ++j)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const unsigned long long m = __ballot(s[j][q]);
-                mine[j][q] = cnt + (uint32_t)__popcll(m & lt);
-                cnt += (uint32_t)__popcll(m);
+        for (uint32_t j = 0; j < kRun; ++j) {
+            bool s0, s1;
+            PixBox b0, b1;
+            survive(v, P[j], valid[j], s0, s1, b0, b1, rerr);
+            const unsigned long long m0 = __ballot(s0), m1 = __ballot(s1);
+            const uint32_t c0 = (uint32_t)__popcll(m0), cnt = c0 + (uint32_t)__popcll(m1);
+            if (!cnt) continue;
+            if (nbuf + cnt > kSetupBuf) flush();   // cnt <= 2 * 64 <= kSetupBuf
+            if (v.count_work) {
+                uint32_t area = 0;
+                if (s0) area += (uint32_t)(b0.i1 - b0.i0 + 1) * (uint32_t)(b0.j1 - b0.j0 + 1);
+                if (s1) area += (uint32_t)(b1.i1 - b1.i0 + 1) * (uint32_t)(b1.j1 - b1.j0 + 1);
+                // two boxes of at most 2^24 pixels per lane: the two halves
+                // of the wave sum cannot overflow
+                const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
+                const uint32_t ahi = wave_sum_u32(area >> 16);
+                barea += (unsigned long long)alo + ((unsigned long long)ahi << 16);
             }
-        if (!cnt) continue;
-        if (nbuf + cnt > kSetupBuf) flush();   // cnt <= 2 kRun 64 = kSetupBuf
-        if (v.count_work) {
-            uint32_t area = 0;
-#pragma unroll
-            for (uint32_t j = 0; j < kRun; ++j)
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    if (s[j][q])
-                        area += (uint32_t)(bx[j][q].i1 - bx[j][q].i0 + 1) * (uint32_t)(bx[j][q].j1 - bx[j][q].j0 + 1);
-            // eight boxes of at most 2^24 pixels per lane: the two halves
-            // of the wave sum cannot overflow
-            const uint32_t alo = wave_sum_u32(area & 0xFFFFu);
-            const uint32_t ahi = wave_sum_u32(area >> 16);
-            barea += (unsigned long long)alo + ((unsigned long long)ahi << 16);
+            if (s0) {
+                const uint32_t k = nbuf + (uint32_t)__popcll(m0 & lt);
+                wkey[k] = 2u * t[j];
+                wbox[k] = pack_box(b0);
+            }
+            if (s1) {
+                const uint32_t k = nbuf + c0 + (uint32_t)__popcll(m1 & lt);
+                wkey[k] = 2u * t[j] + 1u;
+                wbox[k] = pack_box(b1);
+            }
+            nbuf += cnt;
         }
-#pragma unroll
-        for (uint32_t j = 0; j < kRun; ++j)
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-                if (s[j][q]) {
-                    wkey[nbuf + mine[j][q]] = 2u * t[j] + (uint32_t)q;
-                    wbox[nbuf + mine[j][q]] = pack_box(bx[j][q]);
-                }
-        nbuf += cnt;
     }
     flush();
     if (rerr) atomicOr(err, kErrRange);
